@@ -1,0 +1,147 @@
+"""Benchmark: grid-point RK4 updates per second of the fused HIP integrator.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the 3D Gross-Pitaevskii problem on a 256^3 grid (harmonic trap,
+Thomas-Fermi background with a vortex ring), FP32 storage with the
+compensated FP64 final RK4 combination, 2SHOC Laplacian, MSD boundaries.  A
+"step" is one full RK4 step (four fused stage kernels) over the whole grid;
+inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line with the throughput, the roofline position of the stage
+kernel (algorithmic bytes / measured time against 8 TB/s HBM) and a CPU
+baseline (the FP64 oracle timed on a bounded sample on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# Algorithmic HBM bytes per grid point per RK4 step (each array touched once
+# per stage; halos and the 2SHOC temporary stay on chip):
+#   S1: r Psi 8, r V 4, w acc 8, w U1 8                      = 28
+#   S2: r U1 8, r V 4, r Psi 8, r/w acc 16, w U2 8           = 44
+#   S3: same as S2                                           = 44
+#   S4 (compensated): r U3 8, V 4, acc 8, Psi_hi 8, Psi_lo 8,
+#       w Psi_hi 8, w Psi_lo 8                               = 52
+BYTES_PER_PT_STEP = {"compensated": 168, "plain": 144}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256, help="grid extent per axis (default 256)")
+    ap.add_argument("--plain", action="store_true", help="plain FP32 (no compensation)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=0,
+                    help="oracle steps for the CPU baseline (0 = pick ~15 s of work)")
+    return ap.parse_args()
+
+
+def cpu_baseline(problem, dt, steps_hint):
+    """Time the FP64 oracle as it stands on a bounded sample of the workload."""
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n = steps_hint if steps_hint > 0 else 0
+    if n == 0:
+        # one calibration step, then enough steps for ~15 s of CPU work
+        t0 = time.perf_counter()
+        oracle.rk4(problem.psi0, problem.h, problem.a, problem.s, dt, 1, V=problem.V,
+                   order=problem.order, bc=problem.bc)
+        one = time.perf_counter() - t0
+        n = max(1, min(50, int(15.0 / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.rk4(problem.psi0, problem.h, problem.a, problem.s, dt, n, V=problem.V,
+               order=problem.order, bc=problem.bc)
+    el = time.perf_counter() - t0
+    return {"value": problem.npts * n / el, "unit": "grid-point RK4 updates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{'x'.join(map(str, problem.psi0.shape[::-1]))} grid, {n} RK4 steps, "
+                      f"2SHOC+MSD, FP64, {cores} OpenMP threads, {el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1203_1263_amd import workloads as wl
+    from paper_1203_1263_amd.nlse import Grid, nlse_dt_max, NLSE_2SHOC
+
+    comp = not args.plain
+    n = args.n
+    h = 0.1 * 256 / n
+    prob = wl.ring3d(shape=(n, n, n), h=h)
+    dt = 0.8 * nlse_dt_max(3, 4, h, prob.a)
+    psi = torch.from_numpy(prob.psi0.astype(np.complex64)).cuda()
+    V = torch.from_numpy(prob.V.astype(np.float32)).cuda()
+    stream = torch.cuda.current_stream()
+    g = Grid(psi, h, prob.a, prob.s, V=V, compensated=comp, stream=stream)
+    g.autotune(NLSE_2SHOC, "msd", dt)
+    tile = g.tile(NLSE_2SHOC)
+    g.step(dt, args.warmup, order=NLSE_2SHOC, bc="msd")
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    g.step(dt, args.steps, order=NLSE_2SHOC, bc="msd")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    M, E = g.mass_energy(NLSE_2SHOC, "msd")
+    npts = prob.npts
+    value = npts * args.steps / wall
+    bpp = BYTES_PER_PT_STEP["compensated" if comp else "plain"]
+    launches = 4 * args.steps
+    avg_launch_s = gpu_ms * 1e-3 / launches
+    bytes_per_launch = npts * bpp / 4.0
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    out = {
+        "metric": "grid-point RK4 updates/s (3D 2SHOC FP32, 256^3)",
+        "value": value,
+        "unit": "grid-point RK4 updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" + ("+f64-compensated" if comp else ""),
+        "data": "synthetic",
+        "config": {"workload": f"ring3d_{n}^3_2shoc_msd_{'compensated' if comp else 'plain'}_fp32",
+                   "grid": [n, n, n], "h": h, "a": prob.a, "s": prob.s, "dt": dt,
+                   "tile": list(tile), "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage3d_kernel<float,2SHOC,MSD>",
+                     "bytes_per_point_step": bpp,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "mass": M, "energy": E,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, float(dt), args.cpu_steps)
+    g.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,153 @@
+/*
+ * nlse.h -- C ABI of libnlse, an MI355X (gfx950) integrator for the
+ * nonlinear Schroedinger / Gross-Pitaevskii equation
+ *
+ *     i Psi_t + a Lap(Psi) - V Psi + s |Psi|^2 Psi = 0          (Eq. NLSE)
+ *
+ * advanced by classic RK4 (Eq. RK4) with the right-hand side
+ * F(Psi) = i [ a L Psi + (s|Psi|^2 - V) Psi ], where L is the second-order
+ * central difference (CD2, step 1 of Eqs. 2shoc1d / 2d2shocs1 / 3d2shocs) or
+ * the fourth-order two-step compact scheme 2SHOC (Eqs. 2shoc1d2 / 2d2shocs2 /
+ * 3d2shocs2), and boundary points follow Dirichlet (Eqs. BCDdt, BCDlap) or
+ * modulus-squared Dirichlet (Eqs. msd, BCMSDlap) conditions.
+ * (Caplan, "NLSEmagic", arXiv:1203.1263, Secs. "Finite-difference schemes",
+ * "Boundary conditions", "Stability".)
+ *
+ * Conventions for every function below
+ * -------------------------------------
+ *  - Grids: ndim in {1,2,3}; dims = {Nx, Ny, Nz}, entries beyond ndim must be
+ *    1; every active extent must be >= 3.  Equal spacing h in all directions
+ *    (Sec. "Finite-difference schemes").  Every point with an active index 0
+ *    or N-1 is a boundary point.
+ *  - Layout: interleaved complex (re, im), x fastest, linear index
+ *    x + Nx*(y + Ny*z); FP32 fields are float2 arrays, FP64 fields double2.
+ *    A potential V is a real array of the same element type and shape.
+ *  - Device pointers are HIP device addresses (e.g. from a torch CUDA tensor
+ *    under ROCm); "borrowed" buffers stay owned by the caller and must
+ *    outlive the object that references them.
+ *  - Streams: hip_stream is a hipStream_t passed as void*; NULL = the legacy
+ *    default stream.  All work is enqueued asynchronously on that stream
+ *    unless a function says it synchronises.
+ *  - Errors: 0 on success, a negative nlse_status otherwise.  Arguments are
+ *    validated before anything is launched; on error nothing was enqueued.
+ *    nlse_last_error() returns a thread-local message for the last failure.
+ *  - Threading: objects are not internally locked; use one object per host
+ *    thread (or serialise calls).  Different objects are independent.
+ */
+#ifndef NLSE_H_
+#define NLSE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ constants */
+
+typedef enum {
+    NLSE_OK = 0,
+    NLSE_EINVAL = -1,      /* bad argument (shape, parameter, pointer, size)  */
+    NLSE_ENOMEM = -2,      /* host allocation failed / workspace too small    */
+    NLSE_EDEVICE = -3,     /* a HIP runtime call failed (message has details) */
+    NLSE_EUNSTABLE = -4,   /* non-finite mass or energy: the run blew up      */
+    NLSE_EUNSUPPORTED = -5 /* valid but not implemented combination          */
+} nlse_status;
+
+enum { NLSE_F32 = 0, NLSE_F64 = 1 };               /* element type            */
+enum { NLSE_CD2 = 2, NLSE_2SHOC = 4 };              /* Laplacian order         */
+enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1 };    /* boundary condition      */
+
+/* Grid flags. */
+#define NLSE_COMPENSATED 0x1u /* FP32 only: keep Psi as hi+lo pair, RK4
+                                 combination of the last stage done in FP64 */
+
+typedef struct nlse_grid nlse_grid;
+
+/* ------------------------------------------------------------ utilities */
+
+/* Linear stability bound of RK4 with CD2 (Eq. stblincd):
+ *     k < h^2 / (ndim sqrt(2) a),
+ * and 3/4 of it for 2SHOC (Eq. stblin2shoc).  No safety factor is applied
+ * (the paper's drivers multiply by 0.8).  Returns a negative value for
+ * invalid arguments. */
+double nlse_dt_max(int ndim, int order, double h, double a);
+
+/* Human-readable text for a status code (static storage). */
+const char *nlse_strerror(int status);
+
+/* Thread-local detail message of the last failing call on this thread. */
+const char *nlse_last_error(void);
+
+/* ------------------------------------------------------------ single grid */
+
+/* Size in bytes of the device workspace a grid needs: the RK4 accumulator,
+ * two ping-pong stage buffers, the FP32 compensation term (if
+ * NLSE_COMPENSATED) and reduction partials.  dims as described above. */
+int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype,
+                         unsigned flags, size_t *bytes);
+
+/* Create a grid.
+ *   psi_dev   device buffer of Npts complex values (borrowed; updated in place
+ *             by nlse_step_rk4).
+ *   work_dev  device buffer of >= nlse_workspace_bytes() bytes, 256-byte
+ *             aligned (borrowed; its contents are owned by the grid).
+ *   h, a, s   spacing, dispersion a > 0, nonlinearity s (finite).
+ *   flags     0 or NLSE_COMPENSATED (FP32 only).
+ * The compensation term starts at zero.  Enqueues its initialisation on the
+ * stream.  On success *g receives the new grid. */
+int nlse_create_grid(nlse_grid **g, int ndim, const int64_t dims[3], double h,
+                     double a, double s, int dtype, unsigned flags,
+                     void *psi_dev, void *work_dev, size_t work_bytes,
+                     void *hip_stream);
+
+/* Set (V_dev != NULL, borrowed, real, same element type and shape) or clear
+ * (V_dev == NULL, meaning V == 0) the external potential of Eq. NLSE. */
+int nlse_set_potential(nlse_grid *g, const void *V_dev);
+
+/* Advance nsteps classic RK4 steps of size dt (Eq. RK4) with Laplacian
+ * `order` (NLSE_CD2 or NLSE_2SHOC) and boundary condition `bc`.  Each step is
+ * four fused stage kernels (stencil, boundary update and RK4 accumulation in
+ * one pass each).  Psi is updated in place; asynchronous.  dt > 0 finite,
+ * nsteps >= 0.  A dt above nlse_dt_max() is allowed (blow-up shows up as
+ * NLSE_EUNSTABLE from nlse_mass_energy). */
+int nlse_step_rk4(nlse_grid *g, int order, int bc, double dt, int64_t nsteps);
+
+/* Mass M = h^d sum |Psi|^2 and energy
+ *   E = h^d [ sum_interior -a Re(conj(Psi) L Psi) + sum ( V|Psi|^2 - (s/2)|Psi|^4 ) ]
+ * (the standard NLSE invariants; the paper defines neither), with L the
+ * scheme Laplacian of `order` (2SHOC uses the boundary D of `bc`).  Partial
+ * sums in FP64 per workgroup over a fixed partition, then a fixed-order final
+ * sum: the result is bitwise reproducible.  Synchronises the stream.
+ * Returns NLSE_EUNSTABLE (after writing both values) if either is not
+ * finite. */
+int nlse_mass_energy(nlse_grid *g, int order, int bc, double *mass,
+                     double *energy);
+
+/* Copy the compensation term (Npts complex FP32 values, same layout as Psi)
+ * out to / in from a device buffer.  lo_dev == NULL in nlse_set_state resets
+ * it to zero (call this after overwriting Psi).  Grids without
+ * NLSE_COMPENSATED return NLSE_EINVAL.  Asynchronous. */
+int nlse_get_state(nlse_grid *g, void *lo_dev);
+int nlse_set_state(nlse_grid *g, const void *lo_dev);
+
+/* Tile shape used by the stage kernels: (tx, ty, cz) = x-width, y-height and
+ * z-chunk length (unused entries 1).  Any supported shape gives bitwise
+ * identical results.  nlse_autotune times the candidates for
+ * (order, bc) on this grid (running stage kernels on scratch copies, the
+ * field is not changed), keeps the fastest and stores it in the cache file
+ * named by $NLSE_TUNE_CACHE if set.  nlse_set_tile forces a shape
+ * (NLSE_EUNSUPPORTED if it is not a compiled candidate). */
+int nlse_autotune(nlse_grid *g, int order, int bc, double dt);
+int nlse_get_tile(const nlse_grid *g, int order, int tile[3]);
+int nlse_set_tile(nlse_grid *g, int order, const int tile[3]);
+
+/* Destroy a grid: frees library-internal host objects and graphs only. */
+int nlse_destroy_grid(nlse_grid *g);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NLSE_H_ */

@@ -1,0 +1,501 @@
+// C ABI of libnlse (declared in include/nlse.h): argument validation,
+// workspace carving, stage sequencing and the tile autotuner.  All device
+// work is enqueued on the caller's HIP stream.
+#include "nlse.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nlse_internal.h"
+
+// ---------------------------------------------------------------- errors
+
+static thread_local char g_last_error[512] = "";
+
+static int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* what) {
+  return fail(NLSE_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+extern "C" const char* nlse_last_error(void) { return g_last_error; }
+
+extern "C" const char* nlse_strerror(int status) {
+  switch (status) {
+    case NLSE_OK: return "success";
+    case NLSE_EINVAL: return "invalid argument";
+    case NLSE_ENOMEM: return "out of memory or workspace too small";
+    case NLSE_EDEVICE: return "HIP runtime error";
+    case NLSE_EUNSTABLE: return "non-finite mass or energy (unstable run)";
+    case NLSE_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown status";
+  }
+}
+
+// ---------------------------------------------------------------- shapes
+
+struct Shape {
+  int ndim;
+  int64_t n[3];
+  int64_t npts;
+};
+
+static int check_shape(int ndim, const int64_t dims[3], Shape* s) {
+  if (ndim < 1 || ndim > 3) return fail(NLSE_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+  if (!dims) return fail(NLSE_EINVAL, "dims is NULL");
+  s->ndim = ndim;
+  s->npts = 1;
+  for (int d = 0; d < 3; ++d) {
+    int64_t n = dims[d];
+    if (d < ndim) {
+      if (n < 3) return fail(NLSE_EINVAL, "extent %d is %lld; every active extent must be >= 3", d, (long long)n);
+      if (n > (int64_t)1 << 30) return fail(NLSE_EINVAL, "extent %d is too large", d);
+    } else if (n != 1) {
+      return fail(NLSE_EINVAL, "extent %d must be 1 for a %dD grid", d, ndim);
+    }
+    s->n[d] = n;
+    s->npts *= n;
+  }
+  if (s->n[0] * s->n[1] > ((int64_t)1 << 31) - 1)
+    return fail(NLSE_EINVAL, "a single plane must hold fewer than 2^31 points");
+  return NLSE_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t acc, bufA, bufB, lo, partials, out, total;
+};
+
+static Layout layout_for(const Shape& s, int dtype, unsigned flags) {
+  const size_t esz = dtype == NLSE_F32 ? 8 : 16;
+  const size_t field = align256((size_t)s.npts * esz);
+  Layout L;
+  size_t off = 0;
+  L.acc = off;
+  off += field;
+  L.bufA = off;
+  off += field;
+  L.bufB = off;
+  off += field;
+  L.lo = off;
+  if (flags & NLSE_COMPENSATED) off += field;
+  L.partials = off;
+  off += align256((size_t)nlse::reduce_blocks(s.npts) * 3 * sizeof(double));
+  L.out = off;
+  off += 256;
+  L.total = off;
+  return L;
+}
+
+// ---------------------------------------------------------------- grid
+
+struct nlse_grid {
+  Shape shape;
+  int dtype;
+  unsigned flags;
+  double h, a, s;
+  void* psi;
+  char* work;
+  size_t work_bytes;
+  Layout lay;
+  hipStream_t stream;
+  const void* V;
+  int tile[2][3];  // [0] CD2, [1] 2SHOC
+};
+
+extern "C" double nlse_dt_max(int ndim, int order, double h, double a) {
+  if (ndim < 1 || ndim > 3 || (order != 2 && order != 4) || !(h > 0) || !(a > 0) || !std::isfinite(h) ||
+      !std::isfinite(a))
+    return -1.0;
+  double k = h * h / ((double)ndim * std::sqrt(2.0) * a);
+  return order == 4 ? 0.75 * k : k;
+}
+
+extern "C" int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype, unsigned flags, size_t* bytes) {
+  Shape s;
+  int rc = check_shape(ndim, dims, &s);
+  if (rc) return rc;
+  if (dtype != NLSE_F32 && dtype != NLSE_F64) return fail(NLSE_EINVAL, "dtype must be NLSE_F32 or NLSE_F64");
+  if (flags & ~NLSE_COMPENSATED) return fail(NLSE_EINVAL, "unknown flag bits 0x%x", flags);
+  if ((flags & NLSE_COMPENSATED) && dtype != NLSE_F32)
+    return fail(NLSE_EUNSUPPORTED, "NLSE_COMPENSATED applies to FP32 grids only");
+  if (!bytes) return fail(NLSE_EINVAL, "bytes is NULL");
+  *bytes = layout_for(s, dtype, flags).total;
+  return NLSE_OK;
+}
+
+// Default tile shapes (x-width, y-height, z-chunk) per dimension.
+static void default_tile(const Shape& s, int dtype, int order, int t[3]) {
+  (void)order;
+  if (s.ndim == 1) {
+    t[0] = 256; t[1] = 1; t[2] = 1;
+  } else if (s.ndim == 2) {
+    t[0] = 64; t[1] = 4; t[2] = 1;
+  } else {
+    t[0] = 64; t[1] = 4;
+    // z-chunks: aim for enough workgroups to fill 256 CUs several times over
+    int64_t xy = ((s.n[0] + 63) / 64) * ((s.n[1] + 3) / 4);
+    int64_t nzi = s.n[2] - 2;
+    int64_t want = 4096;
+    int64_t nch = (want + xy - 1) / xy;
+    if (nch < 1) nch = 1;
+    int64_t cz = (nzi + nch - 1) / nch;
+    if (cz < 8) cz = 8;
+    if (cz > nzi) cz = nzi;
+    t[2] = (int)cz;
+    (void)dtype;
+  }
+}
+
+static int tile_slot(int order) { return order == 4 ? 1 : 0; }
+
+extern "C" int nlse_create_grid(nlse_grid** g, int ndim, const int64_t dims[3], double h, double a, double s,
+                                int dtype, unsigned flags, void* psi_dev, void* work_dev, size_t work_bytes,
+                                void* hip_stream) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  *g = nullptr;
+  size_t need = 0;
+  int rc = nlse_workspace_bytes(ndim, dims, dtype, flags, &need);
+  if (rc) return rc;
+  if (!(h > 0) || !std::isfinite(h)) return fail(NLSE_EINVAL, "h must be finite and > 0");
+  if (!(a > 0) || !std::isfinite(a)) return fail(NLSE_EINVAL, "a must be finite and > 0");
+  if (!std::isfinite(s)) return fail(NLSE_EINVAL, "s must be finite");
+  if (!psi_dev) return fail(NLSE_EINVAL, "psi_dev is NULL");
+  if (!work_dev) return fail(NLSE_EINVAL, "work_dev is NULL");
+  if (((uintptr_t)psi_dev) % (dtype == NLSE_F32 ? 8 : 16))
+    return fail(NLSE_EINVAL, "psi_dev is not aligned to one complex element");
+  if (((uintptr_t)work_dev) % 256) return fail(NLSE_EINVAL, "work_dev must be 256-byte aligned");
+  if (work_bytes < need)
+    return fail(NLSE_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", work_bytes, need);
+  nlse_grid* G = new (std::nothrow) nlse_grid();
+  if (!G) return fail(NLSE_ENOMEM, "host allocation failed");
+  check_shape(ndim, dims, &G->shape);
+  G->dtype = dtype;
+  G->flags = flags;
+  G->h = h;
+  G->a = a;
+  G->s = s;
+  G->psi = psi_dev;
+  G->work = static_cast<char*>(work_dev);
+  G->work_bytes = work_bytes;
+  G->lay = layout_for(G->shape, dtype, flags);
+  G->stream = static_cast<hipStream_t>(hip_stream);
+  G->V = nullptr;
+  default_tile(G->shape, dtype, 2, G->tile[0]);
+  default_tile(G->shape, dtype, 4, G->tile[1]);
+  if (flags & NLSE_COMPENSATED) {
+    hipError_t e = nlse_launch_fill_zero(G->work + G->lay.lo, (int64_t)G->shape.npts * 8, G->stream);
+    if (e != hipSuccess) {
+      delete G;
+      return hip_fail(e, "clearing the compensation term");
+    }
+  }
+  *g = G;
+  return NLSE_OK;
+}
+
+extern "C" int nlse_destroy_grid(nlse_grid* g) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  delete g;
+  return NLSE_OK;
+}
+
+extern "C" int nlse_set_potential(nlse_grid* g, const void* V_dev) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  if (V_dev && ((uintptr_t)V_dev) % (g->dtype == NLSE_F32 ? 4 : 8))
+    return fail(NLSE_EINVAL, "V_dev is misaligned");
+  g->V = V_dev;
+  return NLSE_OK;
+}
+
+static int check_scheme(int order, int bc) {
+  if (order != NLSE_CD2 && order != NLSE_2SHOC) return fail(NLSE_EINVAL, "order must be 2 (CD2) or 4 (2SHOC)");
+  if (bc != NLSE_BC_DIRICHLET && bc != NLSE_BC_MSD)
+    return fail(NLSE_EINVAL, "bc must be NLSE_BC_DIRICHLET or NLSE_BC_MSD");
+  return NLSE_OK;
+}
+
+// Enqueue one RK4 step (four stage launches) with the given tile.
+static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt, const int tile[3],
+                               hipStream_t st) {
+  nlse::StageLaunch L;
+  L.ndim = g->shape.ndim;
+  L.dtype = g->dtype;
+  L.order = order;
+  L.bc = bc;
+  for (int d = 0; d < 3; ++d) L.n[d] = g->shape.n[d];
+  L.V = g->V;
+  L.comp = (g->flags & NLSE_COMPENSATED) ? 1 : 0;
+  L.a = g->a;
+  L.s = g->s;
+  L.h = g->h;
+  for (int d = 0; d < 3; ++d) L.tile[d] = tile[d];
+  void* psi = g->psi;
+  void* acc = g->work + g->lay.acc;
+  void* A = g->work + g->lay.bufA;
+  void* B = g->work + g->lay.bufB;
+  void* lo = L.comp ? g->work + g->lay.lo : nullptr;
+  struct {
+    const void* in;
+    void* out;
+    double ca, cn;
+  } seq[4] = {{psi, A, dt / 6.0, dt / 2.0}, {A, B, dt / 3.0, dt / 2.0}, {B, A, dt / 3.0, dt}, {A, psi, dt / 6.0, 0.0}};
+  for (int k = 0; k < 4; ++k) {
+    L.stage = k + 1;
+    L.uin = seq[k].in;
+    L.uout = seq[k].out;
+    L.psi = psi;
+    L.acc = acc;
+    L.lo = lo;
+    L.c_acc = seq[k].ca;
+    L.c_next = seq[k].cn;
+    hipError_t e = nlse_launch_stage(L, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t nsteps) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  int rc = check_scheme(order, bc);
+  if (rc) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(NLSE_EINVAL, "nsteps must be >= 0");
+  const int* tile = g->tile[tile_slot(order)];
+  for (int64_t n = 0; n < nsteps; ++n) {
+    hipError_t e = enqueue_step(g, order, bc, dt, tile, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "stage launch");
+  }
+  return NLSE_OK;
+}
+
+extern "C" int nlse_mass_energy(nlse_grid* g, int order, int bc, double* mass, double* energy) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  int rc = check_scheme(order, bc);
+  if (rc) return rc;
+  if (!mass || !energy) return fail(NLSE_EINVAL, "mass/energy pointers are NULL");
+  nlse::ReduceLaunch R;
+  R.ndim = g->shape.ndim;
+  R.dtype = g->dtype;
+  R.order = order;
+  R.bc = bc;
+  for (int d = 0; d < 3; ++d) R.n[d] = g->shape.n[d];
+  R.psi = g->psi;
+  R.V = g->V;
+  R.a = g->a;
+  R.s = g->s;
+  R.h = g->h;
+  R.partials = reinterpret_cast<double*>(g->work + g->lay.partials);
+  R.out = reinterpret_cast<double*>(g->work + g->lay.out);
+  hipError_t e = nlse_launch_reduce(R, g->stream);
+  if (e != hipSuccess) return hip_fail(e, "reduction launch");
+  double host[3];
+  e = hipMemcpyAsync(host, R.out, sizeof host, hipMemcpyDeviceToHost, g->stream);
+  if (e != hipSuccess) return hip_fail(e, "copying the reduction result");
+  e = hipStreamSynchronize(g->stream);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  const double hd = std::pow(g->h, (double)g->shape.ndim);
+  *mass = hd * host[0];
+  *energy = hd * (host[1] + host[2]);
+  if (!std::isfinite(*mass) || !std::isfinite(*energy))
+    return fail(NLSE_EUNSTABLE, "mass %g / energy %g is not finite", *mass, *energy);
+  return NLSE_OK;
+}
+
+extern "C" int nlse_get_state(nlse_grid* g, void* lo_dev) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  if (!(g->flags & NLSE_COMPENSATED)) return fail(NLSE_EINVAL, "grid has no compensation term");
+  if (!lo_dev) return fail(NLSE_EINVAL, "lo_dev is NULL");
+  hipError_t e = hipMemcpyAsync(lo_dev, g->work + g->lay.lo, (size_t)g->shape.npts * 8, hipMemcpyDeviceToDevice,
+                                g->stream);
+  return e == hipSuccess ? NLSE_OK : hip_fail(e, "copying the compensation term");
+}
+
+extern "C" int nlse_set_state(nlse_grid* g, const void* lo_dev) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  if (!(g->flags & NLSE_COMPENSATED)) return fail(NLSE_EINVAL, "grid has no compensation term");
+  hipError_t e;
+  if (!lo_dev)
+    e = nlse_launch_fill_zero(g->work + g->lay.lo, (int64_t)g->shape.npts * 8, g->stream);
+  else
+    e = hipMemcpyAsync(g->work + g->lay.lo, lo_dev, (size_t)g->shape.npts * 8, hipMemcpyDeviceToDevice, g->stream);
+  return e == hipSuccess ? NLSE_OK : hip_fail(e, "setting the compensation term");
+}
+
+// ---------------------------------------------------------------- tiles / autotuner
+
+extern "C" int nlse_get_tile(const nlse_grid* g, int order, int tile[3]) {
+  if (!g || !tile) return fail(NLSE_EINVAL, "NULL argument");
+  if (order != 2 && order != 4) return fail(NLSE_EINVAL, "bad order");
+  memcpy(tile, g->tile[tile_slot(order)], 3 * sizeof(int));
+  return NLSE_OK;
+}
+
+static bool tile_fits(const nlse_grid* g, const int t[3]) {
+  if (!nlse_internal_tile_supported(g->shape.ndim, g->dtype, t)) return false;
+  // FP64 3D tiles must fit the 64 KiB of LDS a workgroup may use.
+  if (g->shape.ndim == 3 && g->dtype == NLSE_F64 && t[0] == 128) return false;
+  if (g->shape.ndim == 3 && t[2] > g->shape.n[2] - 2) return false;
+  return true;
+}
+
+extern "C" int nlse_set_tile(nlse_grid* g, int order, const int tile[3]) {
+  if (!g || !tile) return fail(NLSE_EINVAL, "NULL argument");
+  if (order != 2 && order != 4) return fail(NLSE_EINVAL, "bad order");
+  if (!tile_fits(g, tile))
+    return fail(NLSE_EUNSUPPORTED, "tile %dx%dx%d is not a compiled candidate for this grid", tile[0], tile[1],
+                tile[2]);
+  memcpy(g->tile[tile_slot(order)], tile, 3 * sizeof(int));
+  return NLSE_OK;
+}
+
+static std::vector<std::array<int, 3>> candidates(const nlse_grid* g) {
+  std::vector<std::array<int, 3>> out;
+  const Shape& s = g->shape;
+  if (s.ndim == 1) {
+    out.push_back({256, 1, 1});
+  } else if (s.ndim == 2) {
+    for (auto t : {std::array<int, 3>{64, 4, 1}, {64, 8, 1}, {128, 4, 1}, {32, 8, 1}}) out.push_back(t);
+  } else {
+    const int64_t nzi = s.n[2] - 2;
+    for (auto xy : {std::array<int, 2>{64, 4}, {64, 2}, {32, 8}, {128, 2}})
+      for (int cz : {8, 16, 32, 64}) {
+        std::array<int, 3> t = {xy[0], xy[1], (int)std::min<int64_t>(cz, nzi)};
+        bool dup = false;
+        for (auto& o : out) dup |= (o == t);
+        if (!dup) out.push_back(t);
+      }
+  }
+  std::vector<std::array<int, 3>> ok;
+  for (auto& t : out)
+    if (tile_fits(g, t.data())) ok.push_back(t);
+  return ok;
+}
+
+static std::string cache_key(const nlse_grid* g, int order, int bc) {
+  char buf[160];
+  snprintf(buf, sizeof buf, "d%d n%lldx%lldx%lld t%d o%d b%d c%d v%d", g->shape.ndim, (long long)g->shape.n[0],
+           (long long)g->shape.n[1], (long long)g->shape.n[2], g->dtype, order, bc,
+           (g->flags & NLSE_COMPENSATED) ? 1 : 0, g->V ? 1 : 0);
+  return buf;
+}
+
+static bool cache_lookup(const std::string& key, int t[3]) {
+  const char* path = getenv("NLSE_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[256];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char* bar = strchr(line, '|');
+    if (!bar) continue;
+    *bar = 0;
+    if (key == line && sscanf(bar + 1, "%d %d %d", &t[0], &t[1], &t[2]) == 3) found = true;
+  }
+  fclose(f);
+  return found;
+}
+
+static void cache_store(const std::string& key, const int t[3], float ms) {
+  const char* path = getenv("NLSE_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "%s|%d %d %d %.6f\n", key.c_str(), t[0], t[1], t[2], ms);
+  fclose(f);
+}
+
+// Times stages 1-3 only (they read Psi but never write it), so the field is
+// left untouched; the accumulator and stage buffers are scratch.
+extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  int rc = check_scheme(order, bc);
+  if (rc) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
+  const std::string key = cache_key(g, order, bc);
+  int cached[3];
+  if (cache_lookup(key, cached) && tile_fits(g, cached)) {
+    memcpy(g->tile[tile_slot(order)], cached, sizeof cached);
+    return NLSE_OK;
+  }
+  auto cands = candidates(g);
+  if (cands.empty()) return fail(NLSE_EUNSUPPORTED, "no tile candidate fits this grid");
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(e, "hipEventCreate");
+  }
+  nlse::StageLaunch L;
+  L.ndim = g->shape.ndim;
+  L.dtype = g->dtype;
+  L.order = order;
+  L.bc = bc;
+  for (int d = 0; d < 3; ++d) L.n[d] = g->shape.n[d];
+  L.V = g->V;
+  L.comp = (g->flags & NLSE_COMPENSATED) ? 1 : 0;
+  L.a = g->a;
+  L.s = g->s;
+  L.h = g->h;
+  L.psi = g->psi;
+  L.acc = g->work + g->lay.acc;
+  L.lo = L.comp ? g->work + g->lay.lo : nullptr;
+  void* A = g->work + g->lay.bufA;
+  void* B = g->work + g->lay.bufB;
+  float best = 1e30f;
+  std::array<int, 3> best_t = cands[0];
+  const int reps = g->shape.npts > (1 << 20) ? 5 : 20;
+  for (auto& t : cands) {
+    for (int d = 0; d < 3; ++d) L.tile[d] = t[d];
+    auto run = [&](int n) -> hipError_t {
+      for (int r = 0; r < n; ++r)
+        for (int k = 1; k <= 3; ++k) {
+          L.stage = k;
+          L.uin = k == 1 ? g->psi : (k == 2 ? A : B);
+          L.uout = k == 2 ? B : A;
+          L.c_acc = k == 1 ? dt / 6.0 : dt / 3.0;
+          L.c_next = k == 3 ? dt : dt / 2.0;
+          hipError_t ee = nlse_launch_stage(L, g->stream);
+          if (ee != hipSuccess) return ee;
+        }
+      return hipSuccess;
+    };
+    if ((e = run(1)) != hipSuccess) break;  // warm-up
+    (void)hipEventRecord(e0, g->stream);
+    if ((e = run(reps)) != hipSuccess) break;
+    (void)hipEventRecord(e1, g->stream);
+    if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(e, "autotune launch");
+  memcpy(g->tile[tile_slot(order)], best_t.data(), 3 * sizeof(int));
+  cache_store(key, best_t.data(), best / reps);
+  return NLSE_OK;
+}

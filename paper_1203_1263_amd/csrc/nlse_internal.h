@@ -1,0 +1,49 @@
+// Internal interfaces between the C-ABI layer (api.cpp) and the kernel
+// translation units of libnlse.  Not installed; no HIP types in the public
+// header.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nlse {
+
+// Everything one stage launch needs.  Element pointers are device addresses
+// of interleaved complex arrays of the grid's element type (dtype 0 = FP32,
+// 1 = FP64); V is real or nullptr.
+struct StageLaunch {
+  int ndim, dtype, order, bc;
+  int64_t n[3];
+  const void* uin;
+  const void* psi;
+  void* acc;
+  void* uout;
+  void* lo;
+  const void* V;
+  int stage, comp;
+  double a, s, h;
+  double c_acc, c_next;
+  int tile[3];
+};
+
+// Mass / energy reduction over one grid.
+struct ReduceLaunch {
+  int ndim, dtype, order, bc;
+  int64_t n[3];
+  const void* psi;
+  const void* V;
+  double a, s, h;
+  double* partials;  // >= reduce_blocks(npts) * 3 doubles
+  double* out;       // 3 doubles: sum rho, sum kinetic, sum potential
+};
+
+constexpr int kReduceChunk = 4096;  // points per reduction workgroup (fixed)
+
+inline int64_t reduce_blocks(int64_t npts) { return (npts + kReduceChunk - 1) / kReduceChunk; }
+
+}  // namespace nlse
+
+hipError_t nlse_launch_stage(const nlse::StageLaunch& L, hipStream_t st);
+hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st);
+hipError_t nlse_launch_fill_zero(void* p, int64_t nbytes, hipStream_t st);
+extern "C" int nlse_internal_tile_supported(int ndim, int dtype, const int tile[3]);

@@ -1,0 +1,79 @@
+"""Write sampled FP64 oracle results for the full-size workloads.
+
+    python tests/golden/make_golden.py [name ...]
+
+The oracle needs minutes (1024^2 x 2000 steps, 87x87x203 x 1000 steps) to
+tens of minutes (256^3 x 1000 steps) on a few CPU cores, too long to rerun in
+every GPU test.  This script runs it once on the seeded inputs of
+``paper_1203_1263_amd.workloads`` and stores, per workload, the values at a
+fixed seeded sample of points (uniform interior samples plus boundary faces,
+edges and corners) together with the oracle's mass, energy and squared L2
+norm of the whole final field.  It calls only ``oracle`` and the input
+generators -- nothing from the GPU path.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1203_1263_amd import workloads as wl  # noqa: E402
+
+
+def problems():
+    return {
+        "c2_vortex2d_1024x1024_2000": lambda: wl.vortex2d(n=1024, h=0.25, nsteps=2000),
+        "c3_ring3d_87x87x203_1000": lambda: wl.ring3d(shape=(203, 87, 87), h=0.14, nsteps=1000),
+        "c3_ring3d_256x256x256_1000": lambda: wl.ring3d(shape=(256, 256, 256), h=0.1, nsteps=1000),
+    }
+
+
+def sample_indices(shape, n_uniform=4096, n_bnd=512, seed=4242):
+    g = np.random.Generator(np.random.PCG64(seed))
+    size = int(np.prod(shape))
+    idx = set(g.integers(0, size, n_uniform).tolist())
+    nd = len(shape)
+    # boundary points: pick a random point, then pin one or more coordinates to an end
+    for _ in range(n_bnd):
+        c = [int(g.integers(0, n)) for n in shape]
+        k = int(g.integers(1, nd + 1))
+        for ax in g.choice(nd, size=k, replace=False):
+            c[ax] = 0 if g.random() < 0.5 else shape[ax] - 1
+        idx.add(int(np.ravel_multi_index(c, shape)))
+    # all corners
+    for corner in np.ndindex(*([2] * nd)):
+        c = [0 if b == 0 else shape[i] - 1 for i, b in enumerate(corner)]
+        idx.add(int(np.ravel_multi_index(c, shape)))
+    return np.array(sorted(idx), dtype=np.int64)
+
+
+def make(name, build):
+    p = build()
+    dt = p.dt_fraction * oracle.dt_max(p.ndim, p.order, p.h, p.a)
+    t0 = time.time()
+    out = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, p.nsteps, V=p.V, order=p.order, bc=p.bc)
+    el = time.time() - t0
+    M, E = oracle.mass_energy(out, p.h, p.a, p.s, V=p.V, order=p.order, bc=p.bc)
+    M0, E0 = oracle.mass_energy(p.psi0, p.h, p.a, p.s, V=p.V, order=p.order, bc=p.bc)
+    idx = sample_indices(p.psi0.shape)
+    flat = out.reshape(-1)
+    np.savez_compressed(
+        os.path.join(HERE, name + ".npz"),
+        idx=idx, val=flat[idx], dt=np.float64(dt), nsteps=np.int64(p.nsteps),
+        shape=np.array(p.psi0.shape, dtype=np.int64), norm2=np.float64(np.sum(np.abs(out) ** 2)),
+        mass=np.float64(M), energy=np.float64(E), mass0=np.float64(M0), energy0=np.float64(E0),
+        oracle_seconds=np.float64(el))
+    print(f"{name}: {el:.1f}s  M0={M0:.12g} M={M:.12g} E0={E0:.12g} E={E:.12g}", flush=True)
+
+
+if __name__ == "__main__":
+    todo = sys.argv[1:] or list(problems())
+    for n in todo:
+        make(n, problems()[n])

@@ -1,0 +1,103 @@
+"""Host-side checks of libnlse (no GPU needed): the library loads, exports
+every function include/nlse.h declares, and validates arguments before it
+touches the device."""
+import ctypes
+import math
+
+import pytest
+
+import oracle
+from paper_1203_1263_amd import nlse
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return nlse.load_library()
+
+
+def test_exports_every_header_symbol(lib):
+    names = nlse.header_symbols()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(lib, n), f"libnlse.so does not export {n}"
+
+
+def test_binding_has_same_names():
+    for n in nlse.header_symbols():
+        if n in ("nlse_strerror", "nlse_last_error"):
+            continue
+        assert callable(getattr(nlse, n, None)), f"binding lacks {n}"
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("order", [2, 4])
+def test_dt_max_matches_oracle(ndim, order):
+    for h, a in ((0.1, 1.0), (0.25, 0.5), (0.14, 0.5)):
+        assert nlse.nlse_dt_max(ndim, order, h, a) == pytest.approx(oracle.dt_max(ndim, order, h, a),
+                                                                     rel=1e-15)
+
+
+def test_dt_max_rejects_bad_args():
+    assert nlse.nlse_dt_max(0, 2, 0.1, 1.0) < 0
+    assert nlse.nlse_dt_max(1, 3, 0.1, 1.0) < 0
+    assert nlse.nlse_dt_max(1, 2, -0.1, 1.0) < 0
+    assert nlse.nlse_dt_max(1, 2, 0.1, 0.0) < 0
+
+
+def test_workspace_sizes():
+    # acc + 2 stage buffers (+ lo) of 8 B/pt for FP32, 16 B/pt for FP64, plus partials
+    n = 256 * 256 * 256
+    b32 = nlse.nlse_workspace_bytes(3, [256, 256, 256], nlse.NLSE_F32)
+    b32c = nlse.nlse_workspace_bytes(3, [256, 256, 256], nlse.NLSE_F32, nlse.NLSE_COMPENSATED)
+    b64 = nlse.nlse_workspace_bytes(3, [256, 256, 256], nlse.NLSE_F64)
+    assert 3 * 8 * n <= b32 < 3 * 8 * n + (1 << 20)
+    assert b32c - b32 == 8 * n
+    assert 3 * 16 * n <= b64 < 3 * 16 * n + (1 << 20)
+
+
+@pytest.mark.parametrize("ndim,dims", [(0, [8, 1, 1]), (4, [8, 1, 1]), (1, [2, 1, 1]), (2, [8, 2, 1]),
+                                       (1, [8, 4, 1]), (3, [8, 8, 0])])
+def test_workspace_rejects_bad_shapes(ndim, dims):
+    with pytest.raises(nlse.NLSEError) as e:
+        nlse.nlse_workspace_bytes(ndim, dims, nlse.NLSE_F32)
+    assert e.value.code == nlse.NLSE_EINVAL
+
+
+def test_compensated_fp64_unsupported():
+    with pytest.raises(nlse.NLSEError) as e:
+        nlse.nlse_workspace_bytes(1, [8, 1, 1], nlse.NLSE_F64, nlse.NLSE_COMPENSATED)
+    assert e.value.code == nlse.NLSE_EUNSUPPORTED
+
+
+def _create(**kw):
+    args = dict(ndim=1, dims=[8, 1, 1], h=0.1, a=1.0, s=1.0, dtype=nlse.NLSE_F32, flags=0,
+                psi_ptr=4096, work_ptr=8192, work_bytes=1 << 20, stream_ptr=None)
+    args.update(kw)
+    return nlse.nlse_create_grid(**args)
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(h=0.0), nlse.NLSE_EINVAL), (dict(h=float("nan")), nlse.NLSE_EINVAL),
+    (dict(a=-1.0), nlse.NLSE_EINVAL), (dict(s=float("inf")), nlse.NLSE_EINVAL),
+    (dict(psi_ptr=None), nlse.NLSE_EINVAL), (dict(work_ptr=None), nlse.NLSE_EINVAL),
+    (dict(work_ptr=8200), nlse.NLSE_EINVAL), (dict(psi_ptr=4100), nlse.NLSE_EINVAL),
+    (dict(work_bytes=16), nlse.NLSE_ENOMEM), (dict(dtype=7), nlse.NLSE_EINVAL),
+    (dict(flags=0x10), nlse.NLSE_EINVAL),
+])
+def test_create_grid_validates_before_launch(bad, code):
+    """Every invalid argument is rejected on the host; nothing is launched."""
+    with pytest.raises(nlse.NLSEError) as e:
+        _create(**bad)
+    assert e.value.code == code
+    assert nlse.load_library().nlse_last_error()
+
+
+def test_null_grid_is_rejected(lib):
+    assert lib.nlse_step_rk4(None, 2, 0, 0.1, 1) == nlse.NLSE_EINVAL
+    assert lib.nlse_destroy_grid(None) == nlse.NLSE_EINVAL
+    assert lib.nlse_set_potential(None, None) == nlse.NLSE_EINVAL
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.nlse_strerror(code)

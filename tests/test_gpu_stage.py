@@ -1,0 +1,254 @@
+"""GPU parity of the fused RK4 stage kernels against the FP64 CPU oracle.
+
+Tolerances:
+* FP32 (plain and compensated): relative L2 <= 1e-5 against the FP64 oracle,
+  the bound the integrator is specified to meet after 1000 steps, applied at
+  every step count tested here.
+* FP64: relative L2 <= 1e-11.  Derivation: the rounding of one RK4 step is a
+  few ulps (u = 1.1e-16) amplified by at most |k lambda| <= 2 sqrt 2 and the
+  stencil weights (sum of |coefficients| <= 30 for 3D 2SHOC); over n <= 1000
+  steps that bounds the drift by ~ n * 30 * u = 3.3e-12 -> 1e-11.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1203_1263_amd import workloads as wl
+from gpu_util import rel_l2, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f64": 1e-11}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1203_1263_amd import nlse
+    nlse.load_library()
+
+
+def smooth_problem(shape, index, V=True, s=-0.9, a=0.7, h=0.3):
+    """Smooth random field with modulus bounded away from 0 (safe for MSD)."""
+    u = 1.5 + 0.4 * wl.random_field(shape, index, smooth=2.0)
+    Vf = 0.3 * wl.random_field(shape, index, stream=1, smooth=3.0).real if V else None
+    return u, Vf, h, a, s
+
+
+# ---------------------------------------------------------------- ragged multi-tile parity
+
+SHAPES = {
+    1: [(600,), (5,), (256,), (1030,)],
+    2: [(37, 150), (3, 3), (5, 70), (9, 64)],
+    3: [(21, 13, 70), (3, 3, 3), (11, 5, 66), (6, 9, 8)],
+}
+CASES = [(nd, shp, order, bc) for nd in (1, 2, 3) for shp in SHAPES[nd] for order in (2, 4)
+         for bc in ("dirichlet", "msd")]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("nd,shape,order,bc", CASES,
+                         ids=[f"{c[0]}d-{'x'.join(map(str, c[1]))}-o{c[2]}-{c[3]}" for c in CASES])
+def test_stage_parity_small(nd, shape, order, bc, dtype):
+    u, V, h, a, s = smooth_problem(shape, 100 + nd)
+    dt = 0.5 * oracle.dt_max(nd, order, h, a)
+    n = 12
+    ref = oracle.rk4(u, h, a, s, dt, n, V=V, order=order, bc=bc)
+    got = run_gpu(u, h, a, s, dt, n, V=V, order=order, bc=bc, dtype=dtype)
+    assert rel_l2(got, ref) < TOL[dtype]
+    if dtype == "f32":
+        got_c = run_gpu(u, h, a, s, dt, n, V=V, order=order, bc=bc, dtype=dtype, compensated=True)
+        assert rel_l2(got_c, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("nd", [1, 2, 3])
+def test_no_potential_matches_zero_potential(nd):
+    shape = SHAPES[nd][0]
+    u, _, h, a, s = smooth_problem(shape, 7, V=False)
+    dt = 0.5 * oracle.dt_max(nd, 4, h, a)
+    g0 = run_gpu(u, h, a, s, dt, 5, V=None, dtype="f64")
+    g1 = run_gpu(u, h, a, s, dt, 5, V=np.zeros(shape), dtype="f64")
+    assert np.array_equal(g0, g1)
+
+
+# ---------------------------------------------------------------- bitwise properties
+
+def _tiles(nd):
+    if nd == 2:
+        return [(64, 4, 1), (64, 8, 1), (128, 4, 1), (32, 8, 1)]
+    return [(64, 4, 8), (64, 2, 5), (32, 8, 3), (128, 2, 16), (64, 4, 1)]
+
+
+@pytest.mark.parametrize("nd", [2, 3])
+@pytest.mark.parametrize("order,bc", [(2, "dirichlet"), (4, "msd")])
+def test_tile_shape_bit_invariance(nd, order, bc):
+    """Every tile shape the autotuner may choose yields identical bits."""
+    shape = (70, 131) if nd == 2 else (19, 21, 133)
+    u, V, h, a, s = smooth_problem(shape, 40 + nd)
+    dt = 0.5 * oracle.dt_max(nd, order, h, a)
+    outs = [run_gpu(u, h, a, s, dt, 6, V=V, order=order, bc=bc, dtype="f32", compensated=True, tile=t)
+            for t in _tiles(nd)]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_run_twice_bitwise():
+    u, V, h, a, s = smooth_problem((17, 23, 91), 3)
+    dt = 0.5 * oracle.dt_max(3, 4, h, a)
+    a1 = run_gpu(u, h, a, s, dt, 8, V=V, order=4, bc="msd", dtype="f32", compensated=True)
+    a2 = run_gpu(u, h, a, s, dt, 8, V=V, order=4, bc="msd", dtype="f32", compensated=True)
+    assert np.array_equal(a1, a2)
+
+
+def test_autotune_keeps_field_and_bits():
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem((20, 30, 140), 11)
+    dt = 0.5 * oracle.dt_max(3, 4, h, a)
+    psi = to_dev(u, "f32")
+    before = psi.clone()
+    g = Grid(psi, h, a, s, V=pot_dev(V, "f32"), compensated=True)
+    g.autotune(4, "msd", dt)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, before)
+    g.step(dt, 5, order=4, bc="msd")
+    tuned = psi.cpu().numpy()
+    ref = run_gpu(u, h, a, s, dt, 5, V=V, order=4, bc="msd", dtype="f32", compensated=True,
+                  tile=(64, 4, 8))
+    assert np.array_equal(tuned.astype(np.complex128), ref)
+
+
+def test_checkpoint_restore_bitwise():
+    """10 steps = 5 steps + (Psi, Psi_lo) saved into a fresh grid + 5 steps."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem((33, 70), 12)
+    dt = 0.5 * oracle.dt_max(2, 4, h, a)
+    psi = to_dev(u, "f32")
+    Vd = pot_dev(V, "f32")
+    g = Grid(psi, h, a, s, V=Vd, compensated=True)
+    g.step(dt, 5, order=4, bc="msd")
+    psi_mid = psi.clone()
+    lo_mid = g.get_state()
+    g.step(dt, 5, order=4, bc="msd")
+    straight = psi.clone()
+    psi2 = psi_mid.clone()
+    g2 = Grid(psi2, h, a, s, V=Vd, compensated=True)
+    g2.set_state(lo_mid)
+    g2.step(dt, 5, order=4, bc="msd")
+    torch.cuda.synchronize()
+    assert torch.equal(psi2, straight)
+    assert torch.count_nonzero(lo_mid) > 0
+
+
+# ---------------------------------------------------------------- mass / energy
+
+@pytest.mark.parametrize("nd,shape", [(1, (600,)), (2, (37, 150)), (3, (21, 13, 70))])
+@pytest.mark.parametrize("order,bc", [(2, "dirichlet"), (4, "msd"), (4, "dirichlet")])
+def test_mass_energy_parity(nd, shape, order, bc):
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem(shape, 60 + nd)
+    M, E = oracle.mass_energy(u, h, a, s, V=V, order=order, bc=bc)
+    for dtype in ("f64", "f32"):
+        uu = u.astype(np.complex64).astype(np.complex128) if dtype == "f32" else u
+        VV = V.astype(np.float32).astype(np.float64) if dtype == "f32" else V
+        Mr, Er = oracle.mass_energy(uu, h, a, s, V=VV, order=order, bc=bc)
+        g = Grid(to_dev(u, dtype), h, a, s, V=pot_dev(V, dtype))
+        Mg, Eg = g.mass_energy(order, bc)
+        # the reduction runs in FP64 on the stored values: FP64-level agreement
+        assert Mg == pytest.approx(Mr, rel=1e-12)
+        assert Eg == pytest.approx(Er, rel=1e-11, abs=1e-11 * abs(Mr))
+        assert Mg == pytest.approx(M, rel=1e-6 if dtype == "f32" else 1e-14)
+        # bitwise reproducible
+        assert g.mass_energy(order, bc) == (Mg, Eg)
+
+
+def test_unstable_run_reports_eunstable():
+    from paper_1203_1263_amd import nlse
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev
+    u, _, h, a, s = smooth_problem((64, 64), 5, V=False)
+    g = Grid(to_dev(u, "f32"), h, a, s)
+    g.step(4.0 * oracle.dt_max(2, 2, h, a), 400, order=2, bc="dirichlet")
+    with pytest.raises(nlse.NLSEError) as e:
+        g.mass_energy(2, "dirichlet")
+    assert e.value.code == nlse.NLSE_EUNSTABLE
+
+
+# ---------------------------------------------------------------- full workloads
+
+@pytest.mark.parametrize("order,expected", [(2, 1.03e-2), (4, 4.61e-5)])
+def test_c1_soliton_fp64(order, expected):
+    """1D bright soliton, N=1024, FP64, Dirichlet, 1000 steps at 0.8 of the bound."""
+    p = wl.soliton1d(order=order)
+    dt = 0.8 * oracle.dt_max(1, order, p.h, p.a)
+    ref = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, 1000, order=order, bc="dirichlet")
+    got = run_gpu(p.psi0, p.h, p.a, p.s, dt, 1000, order=order, bc="dirichlet", dtype="f64")
+    assert rel_l2(got, ref) < TOL["f64"]
+    ex = wl.soliton1d_exact(p.meta["x"], 1000 * dt)
+    assert rel_l2(got, ex) == pytest.approx(expected, rel=0.05)
+
+
+def test_c2_full_size_short_run_full_field():
+    """1024^2 vortex field, FP32 compensated, 10 steps: whole-field parity."""
+    p = wl.vortex2d(n=1024)
+    dt = 0.8 * oracle.dt_max(2, 4, p.h, p.a)
+    ref = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, 10, order=4, bc="msd")
+    got = run_gpu(p.psi0, p.h, p.a, p.s, dt, 10, order=4, bc="msd", dtype="f32", compensated=True)
+    assert rel_l2(got, ref) < TOL["f32"]
+
+
+def _golden(name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return dict(np.load(path, allow_pickle=False))
+
+
+def _golden_case(name, problem, dtype, compensated, autotune=True):
+    G = _golden(name)
+    dt = p_dt = problem.dt_fraction * oracle.dt_max(problem.ndim, problem.order, problem.h, problem.a)
+    assert p_dt == float(G["dt"])
+    got, g = run_gpu(problem.psi0, problem.h, problem.a, problem.s, dt, int(G["nsteps"]), V=problem.V,
+                     order=problem.order, bc=problem.bc, dtype=dtype, compensated=compensated,
+                     autotune=autotune, return_grid=True)
+    flat = got.reshape(-1)
+    idx = G["idx"]
+    err = rel_l2(flat[idx], G["val"])
+    M, E = g.mass_energy(problem.order, problem.bc)
+    g.close()
+    return err, M, E, G
+
+
+@pytest.mark.parametrize("compensated", [True, False])
+def test_c2_vortex_2000_steps_vs_oracle(compensated):
+    """1024^2, FP32 2SHOC + MSD, 2000 steps, sampled against the FP64 oracle."""
+    err, M, E, G = _golden_case("c2_vortex2d_1024x1024_2000", wl.vortex2d(n=1024), "f32", compensated)
+    print(f"c2 compensated={compensated}: sampled rel L2 {err:.3e}")
+    assert err < TOL["f32"]
+    assert M == pytest.approx(float(G["mass"]), rel=1e-5)
+    assert E == pytest.approx(float(G["energy"]), rel=1e-4)
+
+
+def test_c2_vortex_fp64_check():
+    err, M, E, G = _golden_case("c2_vortex2d_1024x1024_2000", wl.vortex2d(n=1024), "f64", False)
+    assert err < TOL["f64"]
+
+
+@pytest.mark.parametrize("name,shape,h", [("c3_ring3d_87x87x203_1000", (203, 87, 87), 0.14),
+                                          ("c3_ring3d_256x256x256_1000", (256, 256, 256), 0.1)])
+def test_c3_ring_1000_steps_vs_oracle(name, shape, h):
+    """3D GPE with a vortex ring, FP32 compensated 2SHOC + MSD, 1000 steps."""
+    err, M, E, G = _golden_case(name, wl.ring3d(shape=shape, h=h), "f32", True)
+    print(f"{name}: sampled rel L2 {err:.3e}")
+    assert err < TOL["f32"]
+    assert M == pytest.approx(float(G["mass"]), rel=1e-5)
