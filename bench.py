@@ -46,7 +46,28 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps for the CPU baseline (0 = pick ~15 s of work)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of exactly 1 GiB, 10 times: reference
+    for the FETCH_SIZE / WRITE_SIZE counters and for achievable bandwidth."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * (1 << 30) * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    print(json.dumps({"copy_probe_bytes_each_way": 1 << 30, "copies": 10, "GB/s": gbs}), flush=True)
 
 
 def cpu_baseline(problem, dt, steps_hint):
@@ -77,6 +98,9 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
     import torch
     from paper_1203_1263_amd import workloads as wl
     from paper_1203_1263_amd.nlse import Grid, nlse_dt_max, NLSE_2SHOC

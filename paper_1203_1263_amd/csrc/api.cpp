@@ -80,7 +80,7 @@ static int check_shape(int ndim, const int64_t dims[3], Shape* s) {
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t acc, bufA, bufB, lo, partials, out, total;
+  size_t acc, bufA, bufB, lo, partials, out, zero, total;
 };
 
 static Layout layout_for(const Shape& s, int dtype, unsigned flags) {
@@ -99,6 +99,8 @@ static Layout layout_for(const Shape& s, int dtype, unsigned flags) {
   L.partials = off;
   off += align256((size_t)nlse::reduce_blocks(s.npts) * 3 * sizeof(double));
   L.out = off;
+  off += 256;
+  L.zero = off;  // 256 zero bytes: stands in for V when there is no potential
   off += 256;
   L.total = off;
   return L;
@@ -149,11 +151,11 @@ static void default_tile(const Shape& s, int dtype, int order, int t[3]) {
   } else if (s.ndim == 2) {
     t[0] = 64; t[1] = 4; t[2] = 1;
   } else {
-    t[0] = 64; t[1] = 4;
+    t[0] = 32; t[1] = 8;
     // z-chunks: aim for enough workgroups to fill 256 CUs several times over
-    int64_t xy = ((s.n[0] + 63) / 64) * ((s.n[1] + 3) / 4);
+    int64_t xy = ((s.n[0] + 31) / 32) * ((s.n[1] + 7) / 8);
     int64_t nzi = s.n[2] - 2;
-    int64_t want = 4096;
+    int64_t want = 2048;
     int64_t nch = (want + xy - 1) / xy;
     if (nch < 1) nch = 1;
     int64_t cz = (nzi + nch - 1) / nch;
@@ -200,12 +202,12 @@ extern "C" int nlse_create_grid(nlse_grid** g, int ndim, const int64_t dims[3], 
   G->V = nullptr;
   default_tile(G->shape, dtype, 2, G->tile[0]);
   default_tile(G->shape, dtype, 4, G->tile[1]);
-  if (flags & NLSE_COMPENSATED) {
-    hipError_t e = nlse_launch_fill_zero(G->work + G->lay.lo, (int64_t)G->shape.npts * 8, G->stream);
-    if (e != hipSuccess) {
-      delete G;
-      return hip_fail(e, "clearing the compensation term");
-    }
+  hipError_t e = nlse_launch_fill_zero(G->work + G->lay.zero, 256, G->stream);
+  if (e == hipSuccess && (flags & NLSE_COMPENSATED))
+    e = nlse_launch_fill_zero(G->work + G->lay.lo, (int64_t)G->shape.npts * 8, G->stream);
+  if (e != hipSuccess) {
+    delete G;
+    return hip_fail(e, "clearing workspace");
   }
   *g = G;
   return NLSE_OK;
@@ -242,6 +244,7 @@ static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt,
   L.bc = bc;
   for (int d = 0; d < 3; ++d) L.n[d] = g->shape.n[d];
   L.V = g->V;
+  L.vzero = g->work + g->lay.zero;
   L.comp = (g->flags & NLSE_COMPENSATED) ? 1 : 0;
   L.a = g->a;
   L.s = g->s;
@@ -348,34 +351,47 @@ extern "C" int nlse_get_tile(const nlse_grid* g, int order, int tile[3]) {
   return NLSE_OK;
 }
 
-static bool tile_fits(const nlse_grid* g, const int t[3]) {
+// LDS bytes of the 3D stage kernel for a tile (must match stage.hip): a ring
+// of stage-input planes with halo plus, for 2SHOC, three D planes.
+static size_t lds_bytes_3d(int order, int dtype, int tx, int ty) {
+  const size_t esz = dtype == NLSE_F32 ? 8 : 16;
+  const int H = order == 4 ? 2 : 1;
+  const int ns = order == 4 ? 6 : 4;
+  size_t b = (size_t)ns * (tx + 2 * H) * (ty + 2 * H);
+  if (order == 4) b += 3 * (size_t)(tx + 2) * (ty + 2);
+  return b * esz;
+}
+
+static bool tile_fits(const nlse_grid* g, int order, const int t[3]) {
   if (!nlse_internal_tile_supported(g->shape.ndim, g->dtype, t)) return false;
-  // FP64 3D tiles must fit the 64 KiB of LDS a workgroup may use.
-  if (g->shape.ndim == 3 && g->dtype == NLSE_F64 && t[0] == 128) return false;
-  if (g->shape.ndim == 3 && t[2] > g->shape.n[2] - 2) return false;
+  if (g->shape.ndim == 3) {
+    if (t[2] > g->shape.n[2] - 2) return false;
+    // keep each workgroup within 64 KiB of LDS so several fit on a CU
+    if (lds_bytes_3d(order, g->dtype, t[0], t[1]) > 65536) return false;
+  }
   return true;
 }
 
 extern "C" int nlse_set_tile(nlse_grid* g, int order, const int tile[3]) {
   if (!g || !tile) return fail(NLSE_EINVAL, "NULL argument");
   if (order != 2 && order != 4) return fail(NLSE_EINVAL, "bad order");
-  if (!tile_fits(g, tile))
+  if (!tile_fits(g, order, tile))
     return fail(NLSE_EUNSUPPORTED, "tile %dx%dx%d is not a compiled candidate for this grid", tile[0], tile[1],
                 tile[2]);
   memcpy(g->tile[tile_slot(order)], tile, 3 * sizeof(int));
   return NLSE_OK;
 }
 
-static std::vector<std::array<int, 3>> candidates(const nlse_grid* g) {
+static std::vector<std::array<int, 3>> candidates(const nlse_grid* g, int order) {
   std::vector<std::array<int, 3>> out;
   const Shape& s = g->shape;
   if (s.ndim == 1) {
     out.push_back({256, 1, 1});
   } else if (s.ndim == 2) {
-    for (auto t : {std::array<int, 3>{64, 4, 1}, {64, 8, 1}, {128, 4, 1}, {32, 8, 1}}) out.push_back(t);
+    for (auto t : {std::array<int, 3>{32, 8, 1}, {64, 4, 1}, {64, 8, 1}}) out.push_back(t);
   } else {
     const int64_t nzi = s.n[2] - 2;
-    for (auto xy : {std::array<int, 2>{64, 4}, {64, 2}, {32, 8}, {128, 2}})
+    for (auto xy : {std::array<int, 2>{32, 8}, {64, 4}, {64, 8}})
       for (int cz : {8, 16, 32, 64}) {
         std::array<int, 3> t = {xy[0], xy[1], (int)std::min<int64_t>(cz, nzi)};
         bool dup = false;
@@ -385,7 +401,7 @@ static std::vector<std::array<int, 3>> candidates(const nlse_grid* g) {
   }
   std::vector<std::array<int, 3>> ok;
   for (auto& t : out)
-    if (tile_fits(g, t.data())) ok.push_back(t);
+    if (tile_fits(g, order, t.data())) ok.push_back(t);
   return ok;
 }
 
@@ -432,11 +448,11 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
   const std::string key = cache_key(g, order, bc);
   int cached[3];
-  if (cache_lookup(key, cached) && tile_fits(g, cached)) {
+  if (cache_lookup(key, cached) && tile_fits(g, order, cached)) {
     memcpy(g->tile[tile_slot(order)], cached, sizeof cached);
     return NLSE_OK;
   }
-  auto cands = candidates(g);
+  auto cands = candidates(g, order);
   if (cands.empty()) return fail(NLSE_EUNSUPPORTED, "no tile candidate fits this grid");
   hipEvent_t e0, e1;
   hipError_t e = hipEventCreate(&e0);
@@ -453,6 +469,7 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   L.bc = bc;
   for (int d = 0; d < 3; ++d) L.n[d] = g->shape.n[d];
   L.V = g->V;
+  L.vzero = g->work + g->lay.zero;
   L.comp = (g->flags & NLSE_COMPENSATED) ? 1 : 0;
   L.a = g->a;
   L.s = g->s;

@@ -99,8 +99,10 @@ __device__ __forceinline__ int inward(int i, int n) { return i == 0 ? 1 : (i == 
 //   S2: acc += k/3 K2,          out = Psi + k/2 K2      (in = U1)
 //   S3: acc += k/3 K3,          out = Psi + k   K3      (in = U2)
 //   S4: Psi  = acc + k/6 K4                             (in = U3)
-// Plain mode stores Psi inside acc; compensated mode keeps acc as the pure
-// increment and finishes S4 in FP64 on the pair Psi_hi + Psi_lo.
+// Plain mode stores Psi inside acc; compensated mode (COMP) keeps acc as the
+// pure increment and finishes S4 in FP64 on the pair Psi_hi + Psi_lo.
+// The stage number and the mode are template parameters so the memory
+// operations of a stage are straight-line code.
 template <typename T>
 struct StageArgs {
   const cpx<T>* uin;  // stage input (neighbours are read)
@@ -108,54 +110,52 @@ struct StageArgs {
   cpx<T>* acc;        // RK4 accumulator
   cpx<T>* uout;       // next stage input; Psi itself at stage 4
   cpx<T>* lo;         // compensation term (stage 4, compensated)
-  const T* V;         // potential, nullptr for V == 0
+  const T* V;         // potential; a one-element zero array when V == 0
+  int64_t vs;         // 1 with a potential, 0 without (V index multiplier)
   int nx, ny, nz;
-  int stage;          // 1..4
-  int comp;           // compensated mode
   Phys<T> ph;
   T c_acc;            // k/6, k/3, k/3, k/6
   T c_next;           // k/2, k/2, k,   (unused)
   double c_acc_d;     // k/6 in FP64 (compensated stage 4)
 };
 
-// Own-point operands of the stage update, loaded early to overlap latency.
+template <typename T>
+__device__ __forceinline__ T vload(const StageArgs<T>& A, int64_t i) {
+  return A.V[i * A.vs];
+}
+
+// Own-point operands of the stage update.
 template <typename T>
 struct Own {
   cpx<T> psi, acc, lo;
 };
 
-template <typename T>
-__device__ __forceinline__ Own<T> load_own(const StageArgs<T>& A, int64_t i) {
-  Own<T> o;
-  o.psi = czero<T>();
-  o.acc = czero<T>();
-  o.lo = czero<T>();
-  if (A.stage == 2 || A.stage == 3) {
+template <typename T, int STAGE, int COMP>
+__device__ __forceinline__ void load_own(const StageArgs<T>& A, int64_t i, Own<T>& o) {
+  if constexpr (STAGE == 2 || STAGE == 3) {
     o.psi = A.psi[i];
     o.acc = A.acc[i];
-  } else if (A.stage == 4) {
+  } else if constexpr (STAGE == 4) {
     o.acc = A.acc[i];
-    if (A.comp) {
+    if constexpr (COMP) {
       o.psi = A.uout[i];
       o.lo = A.lo[i];
     }
   }
-  return o;
 }
 
-template <typename T>
+template <typename T, int STAGE, int COMP>
 __device__ __forceinline__ void stage_update(const StageArgs<T>& A, int64_t i, cpx<T> u, cpx<T> K,
                                              const Own<T>& o) {
   const T ca = A.c_acc, cn = A.c_next;
-  if (A.stage == 1) {
-    cpx<T> acc = A.comp ? mk<T>(ca * K.re, ca * K.im)
-                        : mk<T>(fmaT(ca, K.re, u.re), fmaT(ca, K.im, u.im));
+  if constexpr (STAGE == 1) {
+    cpx<T> acc = COMP ? mk<T>(ca * K.re, ca * K.im) : mk<T>(fmaT(ca, K.re, u.re), fmaT(ca, K.im, u.im));
     A.acc[i] = acc;
     A.uout[i] = mk<T>(fmaT(cn, K.re, u.re), fmaT(cn, K.im, u.im));
-  } else if (A.stage == 2 || A.stage == 3) {
+  } else if constexpr (STAGE == 2 || STAGE == 3) {
     A.acc[i] = mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im));
     A.uout[i] = mk<T>(fmaT(cn, K.re, o.psi.re), fmaT(cn, K.im, o.psi.im));
-  } else if (!A.comp) {
+  } else if constexpr (!COMP) {
     A.uout[i] = mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im));
   } else {
     // Psi_hi + Psi_lo + (acc + k/6 K4), summed in FP64 and split back.

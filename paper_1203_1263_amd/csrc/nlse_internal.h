@@ -20,6 +20,7 @@ struct StageLaunch {
   void* uout;
   void* lo;
   const void* V;
+  const void* vzero;  // device zero of the element type, read when V is null
   int stage, comp;
   double a, s, h;
   double c_acc, c_next;

@@ -1,0 +1,283 @@
+// Fused RK4 stage kernel, 3D, marching along z.
+//
+// One workgroup owns a TX x TY column tile and a chunk [zb, ze) of interior
+// planes (plus plane 0 / nz-1 when the chunk touches them).  LDS holds a ring
+// of stage-input planes with halo (planes z-1 .. z+3 for 2SHOC, z-1 .. z+1 for
+// CD2) and a ring of three 2SHOC D planes (z .. z+2, Eq. 3d2shocs on the tile
+// plus a one-cell ring); the D value of plane z-1 at the thread's column is
+// carried in a register.  Iteration z:
+//   1. issue the loads for iteration z+1 (next stage-input plane into
+//      registers, own operands of plane z+1) -- they stay in flight while
+//      this iteration computes;
+//   2. one barrier;
+//   3. D of plane z+2 into the D ring;
+//   4. L (CD2, or 2SHOC step 2 of Eq. 3d2shocs2), F, boundary forms (Eqs.
+//      BCDdt, BCDlap, msd, BCMSDlap) and the stage update of plane z;
+//   5. the plane loaded one iteration earlier goes into the LDS ring.
+// The loop is unrolled by two with two alternating register sets so no
+// in-flight load is ever copied or overwritten; every load address is
+// clamped into the grid so the memory operations are straight-line code.
+// MSD: a boundary column evaluates F at its interior neighbour column itself
+// (exactly the values the neighbour's thread computes), so no barrier is
+// needed for it; the boundary planes 0 and nz-1 reuse that F at z = 1 / nz-2.
+#include "stage_common.hpp"
+
+namespace nlse {
+
+template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz) {
+  constexpr int NT = TX * TY;
+  constexpr int H = ORDER == 4 ? 2 : 1;
+  constexpr int BW = TX + 2 * H, BH = TY + 2 * H, BSZ = BW * BH;
+  constexpr int LOOK = ORDER == 4 ? 4 : 2;  // plane put into LDS during iteration z is z+LOOK
+  constexpr int NS = LOOK + 2;              // planes z-1 .. z+LOOK
+  constexpr int DW = TX + 2, DH = TY + 2, DSZ = DW * DH;
+  constexpr int PF = (BSZ + NT - 1) / NT;   // plane elements per thread
+  __shared__ cpx<T> sU[NS * BSZ];
+  __shared__ cpx<T> sD[ORDER == 4 ? 3 * DSZ : 1];
+
+  struct Pipe {
+    cpx<T> r[PF];
+    Own<T> own;
+    T vq;
+  };
+
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int64_t ps = (int64_t)nx * ny;
+  const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+  const int t = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tx = t % ntx, ty = (t / ntx) % nty, zc = t / (ntx * nty);
+  const int x0 = tile_origin(tx, TX, nx), y0 = tile_origin(ty, TY, ny);
+  const int tid = threadIdx.x, lx = tid % TX, ly = tid / TX;
+  const int x = x0 + lx, y = y0 + ly;
+  const bool valid = x < nx && y < ny;
+  const bool store = valid && x >= tx * TX && y >= ty * TY;
+  const bool bnd = valid && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1);
+  const int64_t cidx = (int64_t)min(y, ny - 1) * nx + min(x, nx - 1);  // clamped own column
+  // interior column whose F this thread evaluates: its own, or for a
+  // boundary column the MSD neighbour one step inward on each boundary axis
+  const int qlx = lx + (bnd ? inward(x, nx) : 0), qly = ly + (bnd ? inward(y, ny) : 0);
+  const int64_t qidx = valid ? (int64_t)(y0 + qly) * nx + (x0 + qlx) : cidx;
+  const int zb = 1 + zc * cz;
+  const int ze = min(zb + cz, nz - 1);
+  const int zmax = ORDER == 4 ? min(ze + 1, nz - 1) : ze;  // highest plane read
+  const Phys<T>& ph = A.ph;
+  const int ci = (qly + H) * BW + qlx + H;  // q column in a stage-input plane
+  const int di = (qly + 1) * DW + qlx + 1;  // q column in a D plane
+  const int oi = (ly + H) * BW + lx + H;    // own column in a stage-input plane
+
+  auto slot = [&](int z) -> cpx<T>* { return sU + (z % NS) * BSZ; };
+  auto dslot = [&](int z) -> cpx<T>* { return sD + (z % 3) * DSZ; };
+  // element k of a plane box: clamped box index and clamped global offset
+  auto box_index = [&](int k) -> int { return min(tid + k * NT, BSZ - 1); };
+  auto box_goff = [&](int i) -> int64_t {
+    int rr = i / BW, cc = i - rr * BW;
+    int gx = min(max(x0 - H + cc, 0), nx - 1), gy = min(max(y0 - H + rr, 0), ny - 1);
+    return (int64_t)gy * nx + gx;
+  };
+  auto load_regs = [&](int z, cpx<T>(&r)[PF]) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) r[k] = A.uin[(int64_t)z * ps + box_goff(box_index(k))];
+  };
+  auto put_regs = [&](int z, const cpx<T>(&r)[PF]) {
+    cpx<T>* s = slot(z);
+#pragma unroll
+    for (int k = 0; k < PF; ++k) s[box_index(k)] = r[k];
+  };
+  auto load_pipe = [&](int zplane, int zown, Pipe& p) {
+    load_regs(zplane, p.r);
+    load_own<T, STAGE, COMP>(A, (int64_t)zown * ps + cidx, p.own);
+    p.vq = vload(A, (int64_t)zown * ps + qidx);
+  };
+  // CD2 at stage-input position i of plane zp (z-neighbours from LDS too).
+  auto cd2 = [&](int zp, int i) -> cpx<T> {
+    const cpx<T>* P = slot(zp);
+    const cpx<T>* Pm = slot(zp - 1);
+    const cpx<T>* Pp = slot(zp + 1);
+    cpx<T> u = P[i];
+    T sr = T(0), si = T(0);
+    add_diff(sr, si, P[i + 1], u);
+    add_diff(sr, si, P[i - 1], u);
+    add_diff(sr, si, P[i + BW], u);
+    add_diff(sr, si, P[i - BW], u);
+    add_diff(sr, si, Pp[i], u);
+    add_diff(sr, si, Pm[i], u);
+    return mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
+  };
+  // D of plane zp on the tile plus a one-cell ring.  Interior points: CD2.
+  // Boundary points: the Laplacian form of the boundary condition; on the
+  // last plane every point is a boundary point, with its MSD neighbour in
+  // plane zp-1.
+  auto compute_D = [&](int zp) {
+    cpx<T>* Dd = dslot(zp);
+    const bool zbnd = (zp == nz - 1);
+    for (int i = tid; i < DSZ; i += NT) {
+      int r = i / DW, c = i - r * DW;
+      int gx = x0 - 1 + c, gy = y0 - 1 + r;
+      int bi = (r + 1) * BW + c + 1;
+      cpx<T> d = czero<T>();
+      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+        int qx = inward(gx, nx), qy = inward(gy, ny);
+        if (!zbnd && qx == 0 && qy == 0) {
+          d = cd2(zp, bi);
+        } else {
+          cpx<T> ub = slot(zp)[bi];
+          int64_t gi = (int64_t)zp * ps + (int64_t)gy * nx + gx;
+          T Nb = nlin(ph, ub, vload(A, gi));
+          if (BC == kDirichlet) {
+            d = dirichlet_lap(ph, ub, Nb);
+          } else {
+            int qz = zbnd ? -1 : 0;
+            int qi = bi + qy * BW + qx;
+            cpx<T> uq = slot(zp + qz)[qi];
+            int64_t gq = gi + (int64_t)qz * ps + (int64_t)qy * nx + qx;
+            d = msd_lap(ph, cd2(zp + qz, qi), uq, nlin(ph, uq, vload(A, gq)), ub, Nb);
+          }
+        }
+      }
+      Dd[i] = d;
+    }
+  };
+
+  // ---- prologue: planes zb-1 .. zb+LOOK-1 straight into LDS
+  {
+    const int last = min(zb + LOOK - 1, zmax);
+    for (int z = zb - 1; z <= last; ++z) {
+      cpx<T> r[PF];
+      load_regs(z, r);
+      put_regs(z, r);
+    }
+  }
+  cpx<T> um2 = czero<T>();
+  if constexpr (ORDER == 4) um2 = A.uin[(int64_t)max(zb - 2, 0) * ps + qidx];
+  Pipe pa, pb;
+  load_pipe(min(zb + LOOK, zmax), zb, pa);
+  __syncthreads();
+
+  cpx<T> dm = czero<T>();  // D of plane z-1 at the q column
+  if constexpr (ORDER == 4) {
+    if (zb - 1 == 0) {
+      cpx<T> ub = slot(0)[ci];
+      T Nb = nlin(ph, ub, vload(A, qidx));
+      if (BC == kDirichlet) {
+        dm = dirichlet_lap(ph, ub, Nb);
+      } else {
+        cpx<T> uq = slot(1)[ci];
+        dm = msd_lap(ph, cd2(1, ci), uq, nlin(ph, uq, vload(A, ps + qidx)), ub, Nb);
+      }
+    } else {
+      const cpx<T>* P = slot(zb - 1);
+      cpx<T> u = P[ci];
+      T sr = T(0), si = T(0);
+      add_diff(sr, si, P[ci + 1], u);
+      add_diff(sr, si, P[ci - 1], u);
+      add_diff(sr, si, P[ci + BW], u);
+      add_diff(sr, si, P[ci - BW], u);
+      add_diff(sr, si, slot(zb)[ci], u);
+      add_diff(sr, si, um2, u);
+      dm = mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
+    }
+    compute_D(zb);
+    compute_D(zb + 1);
+  }
+
+  auto body = [&](int z, Pipe& cur, Pipe& nxt) {
+    load_pipe(min(z + 1 + LOOK, zmax), min(z + 1, ze - 1), nxt);
+    __syncthreads();
+    if constexpr (ORDER == 4) {
+      if (z + 2 <= ze) compute_D(z + 2);
+    }
+    const cpx<T>* P0 = slot(z);
+    const cpx<T>* Pm = slot(z - 1);
+    const cpx<T>* Pp = slot(z + 1);
+    const cpx<T> u0 = P0[oi];
+    const cpx<T> uq = P0[ci];
+    cpx<T> L;
+    if constexpr (ORDER == 2) {
+      T sr = T(0), si = T(0);
+      add_diff(sr, si, P0[ci + 1], uq);
+      add_diff(sr, si, P0[ci - 1], uq);
+      add_diff(sr, si, P0[ci + BW], uq);
+      add_diff(sr, si, P0[ci - BW], uq);
+      add_diff(sr, si, Pp[ci], uq);
+      add_diff(sr, si, Pm[ci], uq);
+      L = mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
+    } else {
+      const cpx<T>* Dc = dslot(z);
+      cpx<T> D0 = Dc[di];
+      T fr = T(0), fi = T(0);
+      add_diff(fr, fi, Dc[di + 1], D0);
+      add_diff(fr, fi, Dc[di - 1], D0);
+      add_diff(fr, fi, Dc[di + DW], D0);
+      add_diff(fr, fi, Dc[di - DW], D0);
+      add_diff(fr, fi, dslot(z + 1)[di], D0);
+      add_diff(fr, fi, dm, D0);
+      T er = T(0), ei = T(0);
+      add_diff(er, ei, P0[ci + BW + 1], uq);
+      add_diff(er, ei, P0[ci + BW - 1], uq);
+      add_diff(er, ei, P0[ci - BW + 1], uq);
+      add_diff(er, ei, P0[ci - BW - 1], uq);
+      add_diff(er, ei, Pp[ci + 1], uq);
+      add_diff(er, ei, Pp[ci - 1], uq);
+      add_diff(er, ei, Pp[ci + BW], uq);
+      add_diff(er, ei, Pp[ci - BW], uq);
+      add_diff(er, ei, Pm[ci + 1], uq);
+      add_diff(er, ei, Pm[ci - 1], uq);
+      add_diff(er, ei, Pm[ci + BW], uq);
+      add_diff(er, ei, Pm[ci - BW], uq);
+      L = shoc_combine<T, 3>(ph, D0, fr, fi, er, ei);
+    }
+    const cpx<T> Kq = rhs(ph, L, uq, nlin(ph, uq, cur.vq));
+    cpx<T> K = Kq;
+    if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
+    if (store) stage_update<T, STAGE, COMP>(A, (int64_t)z * ps + cidx, u0, K, cur.own);
+    // boundary planes: F_b from the interior neighbour in plane 1 / nz-2
+    if (z == 1 || z == nz - 2) {
+      for (int zz = 0; zz < 2; ++zz) {
+        const int zbp = zz == 0 ? 0 : nz - 1;
+        if ((zz == 0 && z != 1) || (zz == 1 && z != nz - 2)) continue;
+        const int64_t gi = (int64_t)zbp * ps + cidx;
+        Own<T> o;
+        load_own<T, STAGE, COMP>(A, gi, o);
+        const cpx<T> ub = slot(zbp)[oi];
+        const cpx<T> Kb = (BC == kMSD) ? msd_rhs(Kq, uq, ub) : czero<T>();
+        if (store) stage_update<T, STAGE, COMP>(A, gi, ub, Kb, o);
+      }
+    }
+    if constexpr (ORDER == 4) dm = dslot(z)[di];
+    if (z + LOOK <= zmax) put_regs(z + LOOK, cur.r);
+  };
+
+  int z = zb;
+  for (; z + 1 < ze; z += 2) {
+    body(z, pa, pb);
+    body(z + 1, pb, pa);
+  }
+  if (z < ze) body(z, pa, pb);
+}
+
+template <typename T, int O, int B, int S, int C>
+struct Launch3D {
+  static hipError_t run(const StageLaunch& L, hipStream_t st) {
+    StageArgs<T> A = make_args<T>(L);
+    const int tx = L.tile[0], ty = L.tile[1], cz = L.tile[2];
+    if (cz < 1) return hipErrorInvalidValue;
+    const int nb = cdiv(L.n[0], tx) * cdiv(L.n[1], ty) * cdiv(L.n[2] - 2, cz);
+#define NLSE_L3(TX_, TY_)                                                                                  \
+  if (tx == TX_ && ty == TY_) {                                                                            \
+    hipLaunchKernelGGL((stage3d_kernel<T, O, B, S, C, TX_, TY_>), dim3(nb), dim3(TX_ * TY_), 0, st, A, cz); \
+    return hipGetLastError();                                                                              \
+  }
+    NLSE_L3(32, 8)
+    NLSE_L3(64, 4)
+    NLSE_L3(64, 8)
+#undef NLSE_L3
+    return hipErrorInvalidValue;
+  }
+};
+
+}  // namespace nlse
+
+hipError_t nlse_launch_stage_3d(const nlse::StageLaunch& L, hipStream_t st) {
+  return nlse::dispatch_all<nlse::Launch3D>(L, st);
+}
