@@ -34,6 +34,11 @@ HBM_PEAK_GBS = 8000.0
 #   S4 (compensated): r U3 8, V 4, acc 8, Psi_hi 8, Psi_lo 8,
 #       w Psi_hi 8, w Psi_lo 8                               = 52
 BYTES_PER_PT_STEP = {"compensated": 168, "plain": 144}
+# HBM bytes per stage launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE
+# (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0 against a plain 1 GiB copy) for
+# the compensated 256^3 run with tile (32, 8, 16); reported only for that
+# configuration.
+MEASURED_TRAFFIC = {("compensated", 256, (32, 8, 16)): 771.9e6}
 
 
 def parse():
@@ -46,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps for the CPU baseline (0 = pick ~15 s of work)")
+    ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("TX", "TY", "CZ"),
+                    help="stage tile (default: the library's default tile)")
+    ap.add_argument("--autotune", action="store_true", help="let the autotuner pick the tile")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -114,7 +122,10 @@ def main():
     V = torch.from_numpy(prob.V.astype(np.float32)).cuda()
     stream = torch.cuda.current_stream()
     g = Grid(psi, h, prob.a, prob.s, V=V, compensated=comp, stream=stream)
-    g.autotune(NLSE_2SHOC, "msd", dt)
+    if args.tile:
+        g.set_tile(NLSE_2SHOC, args.tile)
+    elif args.autotune:
+        g.autotune(NLSE_2SHOC, "msd", dt)
     tile = g.tile(NLSE_2SHOC)
     g.step(dt, args.warmup, order=NLSE_2SHOC, bc="msd")
     torch.cuda.synchronize()
@@ -155,7 +166,8 @@ def main():
                    "grid": [n, n, n], "h": h, "a": prob.a, "s": prob.s, "dt": dt,
                    "tile": list(tile), "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": MEASURED_TRAFFIC.get(("compensated" if comp else "plain", n, tuple(tile))),
                      "kernel": "stage3d_kernel<float,2SHOC,MSD>",
                      "bytes_per_point_step": bpp,
                      "avg_launch_us": avg_launch_s * 1e6},

@@ -155,7 +155,7 @@ static void default_tile(const Shape& s, int dtype, int order, int t[3]) {
     // z-chunks: aim for enough workgroups to fill 256 CUs several times over
     int64_t xy = ((s.n[0] + 31) / 32) * ((s.n[1] + 7) / 8);
     int64_t nzi = s.n[2] - 2;
-    int64_t want = 2048;
+    int64_t want = 4096;
     int64_t nch = (want + xy - 1) / xy;
     if (nch < 1) nch = 1;
     int64_t cz = (nzi + nch - 1) / nch;
