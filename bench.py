@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("TX", "TY", "CZ"),
                     help="stage tile (default: the library's default tile)")
     ap.add_argument("--autotune", action="store_true", help="let the autotuner pick the tile")
+    ap.add_argument("--workload", choices=["ring3d", "batch2d"], default="ring3d",
+                    help="ring3d: 3D GPE at n^3 (default); batch2d: 512 uneven 2D problems in one launch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -76,6 +78,47 @@ def copy_probe():
     torch.cuda.synchronize()
     gbs = 2 * (1 << 30) * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
     print(json.dumps({"copy_probe_bytes_each_way": 1 << 30, "copies": 10, "GB/s": gbs}), flush=True)
+
+
+def bench_batch(args):
+    """512 independent 2D problems (sizes 64..512 per axis, CD2 or 2SHOC,
+    per-problem a, s, V, dt), compensated FP32, advanced together by the
+    persistent graph-captured kernel; K steps in one launch."""
+    import torch
+    from paper_1203_1263_amd import workloads as wl
+    from paper_1203_1263_amd.nlse import Batch, nlse_dt_max
+    probs = wl.batch2d()
+    dts = [0.8 * nlse_dt_max(2, p.order, p.h, p.a) for p in probs]
+    b = Batch(probs, dts, compensated=not args.plain)
+    b.step(args.steps)  # capture + warm-up with the timed step count
+    b.status()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    b.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.status()
+    gpu_s = ev0.elapsed_time(ev1) * 1e-3
+    info = b.info()
+    npts = info["points"]
+    bpp = BYTES_PER_PT_STEP["plain" if args.plain else "compensated"]
+    achieved = npts * bpp * args.steps / gpu_s / 1e9
+    out = {"metric": "grid-point RK4 updates/s (512 batched 2D problems)", "value": npts * args.steps / wall,
+           "unit": "grid-point RK4 updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.steps,
+           "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" + ("" if args.plain else "+f64-compensated"),
+           "data": "synthetic",
+           "config": {"workload": "batch2d_512_problems_persistent_graph", "points": npts,
+                      "workgroups": info["workgroups"], "items": info["items"]},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "batch2d_kernel (persistent, all stages)", "bytes_per_point_step": bpp}}
+    b.close()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(problem, dt, steps_hint):
@@ -108,6 +151,9 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "batch2d":
+        bench_batch(args)
         return
     import torch
     from paper_1203_1263_amd import workloads as wl

@@ -59,9 +59,11 @@ enum { NLSE_F32 = 0, NLSE_F64 = 1 };               /* element type            */
 enum { NLSE_CD2 = 2, NLSE_2SHOC = 4 };              /* Laplacian order         */
 enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1 };    /* boundary condition      */
 
-/* Grid flags. */
+/* Grid / batch flags. */
 #define NLSE_COMPENSATED 0x1u /* FP32 only: keep Psi as hi+lo pair, RK4
                                  combination of the last stage done in FP64 */
+#define NLSE_NO_GRAPH 0x2u    /* batch only: launch directly instead of
+                                 replaying a captured HIP graph */
 
 typedef struct nlse_grid nlse_grid;
 
@@ -145,6 +147,63 @@ int nlse_set_tile(nlse_grid *g, int order, const int tile[3]);
 
 /* Destroy a grid: frees library-internal host objects and graphs only. */
 int nlse_destroy_grid(nlse_grid *g);
+
+/* ------------------------------------------------------------ batches */
+
+/* Many independent 2D problems of uneven size and parameters advanced
+ * together by one persistent launch per nlse_batch_step_rk4 call (captured
+ * once into a HIP graph per step count and replayed).  Every problem follows
+ * exactly the single-grid integrator above (same scheme, boundary forms and
+ * RK4 stages, Eq. RK4 / Eq. RK4_GPU) with its own a, s, V, h, dt, order and
+ * bc; a problem gives bitwise the same result alone (tile 32x8) as inside a
+ * batch.  Only 2D problems are supported (NLSE_EUNSUPPORTED otherwise). */
+typedef struct {
+    int ndim;            /* must be 2                                       */
+    int64_t dims[3];     /* {Nx, Ny, 1}, Nx, Ny >= 3                        */
+    double h, a, s, dt;  /* spacing, dispersion (> 0), nonlinearity, step   */
+    int order, bc;       /* NLSE_CD2 / NLSE_2SHOC, NLSE_BC_DIRICHLET / _MSD  */
+    int64_t psi_offset;  /* first complex element of this field in psi_pool */
+    int64_t v_offset;    /* first real element of V in v_pool, -1: V == 0   */
+} nlse_sim_desc;
+
+typedef struct nlse_batch nlse_batch;
+
+/* Workspace bytes for a batch (accumulator, stage buffers, compensation,
+ * schedule, reduction scratch). */
+int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc *sims, int dtype,
+                               unsigned flags, size_t *bytes);
+
+/* Create a batch.  psi_pool (psi_pool_elems complex values) and v_pool
+ * (v_pool_elems reals, may be NULL if every v_offset is -1) are borrowed
+ * device pools; each problem's field must lie inside psi_pool and fields must
+ * not overlap (not checked).  work_dev: >= nlse_batch_workspace_bytes bytes,
+ * 256-byte aligned, borrowed.  flags: NLSE_COMPENSATED (FP32), NLSE_NO_GRAPH.
+ * Builds a cost-balanced static schedule of (problem, 32x8 tile) items over
+ * as many workgroups as the device holds at once; synchronises the stream. */
+int nlse_batch_create(nlse_batch **b, int nsims, const nlse_sim_desc *sims,
+                      int dtype, unsigned flags, void *psi_pool,
+                      size_t psi_pool_elems, const void *v_pool,
+                      size_t v_pool_elems, void *work_dev, size_t work_bytes,
+                      void *hip_stream);
+
+/* Advance every problem nsteps RK4 steps with its own dt (asynchronous, one
+ * persistent launch).  A stuck grid-wide barrier (bounded wait) sets an
+ * error flag read by nlse_batch_status. */
+int nlse_batch_step_rk4(nlse_batch *b, int64_t nsteps);
+
+/* Per-problem mass and energy (as nlse_mass_energy, with each problem's own
+ * order and bc) into host arrays of nsims doubles.  Synchronises. */
+int nlse_batch_mass_energy(nlse_batch *b, double *mass, double *energy);
+
+/* Synchronises; NLSE_EDEVICE if a grid-wide barrier of the persistent
+ * kernel timed out since creation, else NLSE_OK. */
+int nlse_batch_status(nlse_batch *b);
+
+/* info[0..3] = workgroups of the persistent launch, work items, total grid
+ * points, captured graphs. */
+int nlse_batch_info(const nlse_batch *b, int64_t info[4]);
+
+int nlse_batch_destroy(nlse_batch *b);
 
 #ifdef __cplusplus
 }

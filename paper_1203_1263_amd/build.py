@@ -32,7 +32,8 @@ COMMON = [
     "-I", INCLUDE, "-I", CSRC,
 ]
 
-SOURCES = ["stage3d.hip", "stage2d.hip", "stage1d.hip", "stage.hip", "reduce.hip", "api.cpp"]
+SOURCES = ["stage3d.hip", "stage2d.hip", "stage1d.hip", "stage.hip", "batch.hip", "reduce.hip", "api.cpp",
+           "api_batch.cpp"]
 
 
 def _compile(src: str) -> str:
@@ -51,7 +52,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs

@@ -22,7 +22,7 @@
 
 static thread_local char g_last_error[512] = "";
 
-static int fail(int code, const char* fmt, ...) {
+int nlse_fail(int code, const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
@@ -30,9 +30,12 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-static int hip_fail(hipError_t e, const char* what) {
-  return fail(NLSE_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+int nlse_hip_fail(hipError_t e, const char* what) {
+  return nlse_fail(NLSE_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
+
+#define fail nlse_fail
+#define hip_fail nlse_hip_fail
 
 extern "C" const char* nlse_last_error(void) { return g_last_error; }
 

@@ -1,0 +1,349 @@
+// C ABI of the batched integrator (declared in include/nlse.h): argument
+// validation, workspace carving, the cost-balanced static schedule, HIP-graph
+// capture of the persistent launch and per-problem reductions.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "api_common.h"
+#include "nlse.h"
+#include "nlse_batch.h"
+#include "nlse_internal.h"
+
+namespace {
+
+constexpr int kMaxChunks = 8192;          // upper bound of persistent workgroups
+constexpr unsigned kSpinLimit = 1u << 25; // bounded barrier wait (~1-2 s)
+
+size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BatchLayout {
+  size_t acc, bufA, bufB, lo, sims, items, chunks, barrier, zero, partials, out, total;
+};
+
+int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, int64_t* total_pts,
+             int64_t* nitems, int64_t* max_blocks) {
+  if (nsims < 1) return nlse_fail(NLSE_EINVAL, "nsims must be >= 1");
+  if (!sims) return nlse_fail(NLSE_EINVAL, "sims is NULL");
+  if (dtype != NLSE_F32 && dtype != NLSE_F64) return nlse_fail(NLSE_EINVAL, "bad dtype");
+  if (flags & ~(NLSE_COMPENSATED | NLSE_NO_GRAPH)) return nlse_fail(NLSE_EINVAL, "unknown flag bits");
+  if ((flags & NLSE_COMPENSATED) && dtype != NLSE_F32)
+    return nlse_fail(NLSE_EUNSUPPORTED, "NLSE_COMPENSATED applies to FP32 only");
+  int64_t tot = 0, items = 0, mb = 1;
+  for (int j = 0; j < nsims; ++j) {
+    const nlse_sim_desc& d = sims[j];
+    if (d.ndim != 2) return nlse_fail(NLSE_EUNSUPPORTED, "problem %d: batches hold 2D problems only", j);
+    if (d.dims[0] < 3 || d.dims[1] < 3 || d.dims[2] != 1 || d.dims[0] > (1 << 30) || d.dims[1] > (1 << 30))
+      return nlse_fail(NLSE_EINVAL, "problem %d: dims must be {Nx>=3, Ny>=3, 1}", j);
+    if ((int64_t)d.dims[0] * d.dims[1] > ((int64_t)1 << 31) - 1)
+      return nlse_fail(NLSE_EINVAL, "problem %d is too large", j);
+    if (!(d.h > 0) || !std::isfinite(d.h) || !(d.a > 0) || !std::isfinite(d.a) || !std::isfinite(d.s))
+      return nlse_fail(NLSE_EINVAL, "problem %d: need h > 0, a > 0, finite s", j);
+    if (!(d.dt > 0) || !std::isfinite(d.dt)) return nlse_fail(NLSE_EINVAL, "problem %d: dt must be > 0", j);
+    if (d.order != NLSE_CD2 && d.order != NLSE_2SHOC) return nlse_fail(NLSE_EINVAL, "problem %d: bad order", j);
+    if (d.bc != NLSE_BC_DIRICHLET && d.bc != NLSE_BC_MSD) return nlse_fail(NLSE_EINVAL, "problem %d: bad bc", j);
+    if (d.psi_offset < 0 || d.v_offset < -1) return nlse_fail(NLSE_EINVAL, "problem %d: bad offsets", j);
+    const int64_t n = d.dims[0] * d.dims[1];
+    tot += n;
+    items += ((d.dims[0] + nlse::kBatchTX - 1) / nlse::kBatchTX) * ((d.dims[1] + nlse::kBatchTY - 1) / nlse::kBatchTY);
+    mb = std::max(mb, nlse::reduce_blocks(n));
+  }
+  if (items > ((int64_t)1 << 31) - 1) return nlse_fail(NLSE_EINVAL, "too many work items");
+  *total_pts = tot;
+  *nitems = items;
+  *max_blocks = mb;
+  return NLSE_OK;
+}
+
+BatchLayout layout(int nsims, int dtype, unsigned flags, int64_t tot, int64_t nitems, int64_t max_blocks) {
+  const size_t esz = dtype == NLSE_F32 ? 8 : 16;
+  const size_t field = a256((size_t)tot * esz);
+  BatchLayout L;
+  size_t off = 0;
+  L.acc = off; off += field;
+  L.bufA = off; off += field;
+  L.bufB = off; off += field;
+  L.lo = off; if (flags & NLSE_COMPENSATED) off += field;
+  L.sims = off; off += a256(sizeof(nlse::BatchSim) * (size_t)nsims);
+  L.items = off; off += a256(sizeof(nlse::BatchItem) * (size_t)nitems);
+  L.chunks = off; off += a256(sizeof(int) * (size_t)(kMaxChunks + 1));
+  L.barrier = off; off += 256;
+  L.zero = off; off += 256;
+  L.partials = off; off += a256((size_t)max_blocks * 3 * sizeof(double));
+  L.out = off; off += a256((size_t)nsims * 3 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct nlse_batch {
+  int nsims, dtype;
+  unsigned flags;
+  std::vector<nlse_sim_desc> desc;
+  std::vector<nlse::BatchSim> sims;
+  int64_t total_pts, nitems;
+  int nchunks;
+  void* psi;
+  const void* vpool;
+  char* work;
+  BatchLayout lay;
+  hipStream_t stream;
+  hipStream_t cap;  // private stream used only for graph capture
+  std::map<int64_t, hipGraphExec_t> graphs;
+};
+
+extern "C" int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags,
+                                          size_t* bytes) {
+  int64_t tot, items, mb;
+  int rc = validate(nsims, sims, dtype, flags, &tot, &items, &mb);
+  if (rc) return rc;
+  if (!bytes) return nlse_fail(NLSE_EINVAL, "bytes is NULL");
+  *bytes = layout(nsims, dtype, flags, tot, items, mb).total;
+  return NLSE_OK;
+}
+
+static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
+  // reset the arrival counter; the error flag next to it stays sticky
+  hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier, 4, st);
+  if (e != hipSuccess) return e;
+  nlse::BatchLaunch L;
+  L.dtype = b->dtype;
+  L.comp = (b->flags & NLSE_COMPENSATED) ? 1 : 0;
+  L.nsteps = (int)nsteps;
+  L.nchunks = b->nchunks;
+  L.sims = reinterpret_cast<const nlse::BatchSim*>(b->work + b->lay.sims);
+  L.items = reinterpret_cast<const nlse::BatchItem*>(b->work + b->lay.items);
+  L.chunk_off = reinterpret_cast<const int*>(b->work + b->lay.chunks);
+  L.psi = b->psi;
+  L.vpool = b->vpool;
+  L.vzero = b->work + b->lay.zero;
+  L.acc = b->work + b->lay.acc;
+  L.bufA = b->work + b->lay.bufA;
+  L.bufB = b->work + b->lay.bufB;
+  L.lo = L.comp ? b->work + b->lay.lo : nullptr;
+  L.barrier = reinterpret_cast<unsigned*>(b->work + b->lay.barrier);
+  L.spin_limit = kSpinLimit;
+  return nlse_launch_batch(L, st);
+}
+
+static void destroy_graphs(nlse_batch* b) {
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags,
+                                 void* psi_pool, size_t psi_pool_elems, const void* v_pool, size_t v_pool_elems,
+                                 void* work_dev, size_t work_bytes, void* hip_stream) {
+  if (!out) return nlse_fail(NLSE_EINVAL, "b is NULL");
+  *out = nullptr;
+  int64_t tot, items, mb;
+  int rc = validate(nsims, sims, dtype, flags, &tot, &items, &mb);
+  if (rc) return rc;
+  if (!psi_pool || !work_dev) return nlse_fail(NLSE_EINVAL, "psi_pool / work_dev is NULL");
+  if (((uintptr_t)work_dev) % 256) return nlse_fail(NLSE_EINVAL, "work_dev must be 256-byte aligned");
+  if (((uintptr_t)psi_pool) % (dtype == NLSE_F32 ? 8 : 16)) return nlse_fail(NLSE_EINVAL, "psi_pool misaligned");
+  BatchLayout L = layout(nsims, dtype, flags, tot, items, mb);
+  if (work_bytes < L.total)
+    return nlse_fail(NLSE_ENOMEM, "workspace of %zu bytes is smaller than the %zu required", work_bytes, L.total);
+  for (int j = 0; j < nsims; ++j) {
+    const int64_t n = sims[j].dims[0] * sims[j].dims[1];
+    if ((size_t)(sims[j].psi_offset + n) > psi_pool_elems)
+      return nlse_fail(NLSE_EINVAL, "problem %d lies outside psi_pool", j);
+    if (sims[j].v_offset >= 0 && (!v_pool || (size_t)(sims[j].v_offset + n) > v_pool_elems))
+      return nlse_fail(NLSE_EINVAL, "problem %d: potential lies outside v_pool", j);
+  }
+
+  // persistent grid: as many workgroups as the device holds at once
+  int dev = 0, cus = 0, occ = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = nlse_batch_occupancy(dtype, (flags & NLSE_COMPENSATED) ? 1 : 0, &occ);
+  if (e != hipSuccess) return nlse_hip_fail(e, "querying occupancy");
+  if (occ < 1 || cus < 1) return nlse_fail(NLSE_EDEVICE, "the batched kernel does not fit on a CU");
+  int64_t nchunks = std::min<int64_t>({(int64_t)occ * cus, items, (int64_t)kMaxChunks});
+
+  nlse_batch* B = new (std::nothrow) nlse_batch();
+  if (!B) return nlse_fail(NLSE_ENOMEM, "host allocation failed");
+  B->nsims = nsims;
+  B->dtype = dtype;
+  B->flags = flags;
+  B->desc.assign(sims, sims + nsims);
+  B->total_pts = tot;
+  B->nitems = items;
+  B->nchunks = (int)nchunks;
+  B->psi = psi_pool;
+  B->vpool = v_pool;
+  B->work = static_cast<char*>(work_dev);
+  B->lay = L;
+  B->stream = static_cast<hipStream_t>(hip_stream);
+  B->cap = nullptr;
+
+  // device descriptors: the same double constants the single-grid path uses
+  std::vector<nlse::BatchSim> ds(nsims);
+  std::vector<nlse::BatchItem> it;
+  std::vector<double> cost;
+  it.reserve((size_t)items);
+  int64_t woff = 0;
+  for (int j = 0; j < nsims; ++j) {
+    const nlse_sim_desc& d = sims[j];
+    nlse::BatchSim& s = ds[j];
+    s.nx = (int)d.dims[0];
+    s.ny = (int)d.dims[1];
+    s.order = d.order;
+    s.bc = d.bc;
+    s.psi_off = d.psi_offset;
+    s.v_off = d.v_offset;
+    s.woff = woff;
+    woff += d.dims[0] * d.dims[1];
+    s.a = d.a;
+    s.s = d.s;
+    s.inv_a = 1.0 / d.a;
+    s.inv_h2 = 1.0 / (d.h * d.h);
+    s.inv_6h2 = 1.0 / (6.0 * d.h * d.h);
+    s.dt = d.dt;
+    s.dt2 = d.dt / 2.0;
+    s.dt3 = d.dt / 3.0;
+    s.dt6 = d.dt / 6.0;
+    const int ntx = (s.nx + nlse::kBatchTX - 1) / nlse::kBatchTX, nty = (s.ny + nlse::kBatchTY - 1) / nlse::kBatchTY;
+    const double c = (d.order == 4 ? 1.35 : 1.0) * (d.v_offset >= 0 ? 1.1 : 1.0);
+    for (int ty = 0; ty < nty; ++ty)
+      for (int tx = 0; tx < ntx; ++tx) {
+        it.push_back({j, tx, ty, 0});
+        cost.push_back(c);
+      }
+  }
+  B->sims = ds;
+  // contiguous chunks of (problem, tile) items with balanced cost
+  std::vector<int> chunk(B->nchunks + 1, (int)items);
+  {
+    double total = 0;
+    for (double c : cost) total += c;
+    double acc = 0;
+    int k = 0;
+    chunk[0] = 0;
+    for (int64_t i = 0; i < items && k + 1 < B->nchunks; ++i) {
+      acc += cost[i];
+      if (acc >= total * (k + 1) / B->nchunks) chunk[++k] = (int)(i + 1);
+    }
+    for (int r = k + 1; r < B->nchunks; ++r) chunk[r] = (int)items;
+    chunk[B->nchunks] = (int)items;
+  }
+  hipStream_t st = B->stream;
+  e = hipMemcpyAsync(B->work + L.sims, ds.data(), sizeof(nlse::BatchSim) * ds.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B->work + L.items, it.data(), sizeof(nlse::BatchItem) * it.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B->work + L.chunks, chunk.data(), sizeof(int) * chunk.size(), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.zero, 256, st);
+  if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.barrier, 256, st);
+  if (e == hipSuccess && (flags & NLSE_COMPENSATED)) e = nlse_launch_fill_zero(B->work + L.lo, tot * 8, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess && !(flags & NLSE_NO_GRAPH)) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete B;
+    return nlse_hip_fail(e, "creating the batch");
+  }
+  *out = B;
+  return NLSE_OK;
+}
+
+extern "C" int nlse_batch_step_rk4(nlse_batch* b, int64_t nsteps) {
+  if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
+  if (nsteps < 0 || nsteps > (1 << 24)) return nlse_fail(NLSE_EINVAL, "nsteps out of range");
+  if (nsteps == 0) return NLSE_OK;
+  hipError_t e;
+  if (b->flags & NLSE_NO_GRAPH) {
+    e = enqueue(b, nsteps, b->stream);
+    return e == hipSuccess ? NLSE_OK : nlse_hip_fail(e, "batch launch");
+  }
+  auto found = b->graphs.find(nsteps);
+  if (found == b->graphs.end()) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return nlse_hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = enqueue(b, nsteps, b->cap);
+    e = hipStreamEndCapture(b->cap, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return nlse_hip_fail(le, "capturing the batch launch");
+    }
+    if (e != hipSuccess) return nlse_hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return nlse_hip_fail(e, "hipGraphInstantiate");
+    found = b->graphs.emplace(nsteps, exec).first;
+  }
+  e = hipGraphLaunch(found->second, b->stream);
+  return e == hipSuccess ? NLSE_OK : nlse_hip_fail(e, "hipGraphLaunch");
+}
+
+extern "C" int nlse_batch_mass_energy(nlse_batch* b, double* mass, double* energy) {
+  if (!b || !mass || !energy) return nlse_fail(NLSE_EINVAL, "NULL argument");
+  double* out = reinterpret_cast<double*>(b->work + b->lay.out);
+  for (int j = 0; j < b->nsims; ++j) {
+    const nlse_sim_desc& d = b->desc[j];
+    nlse::ReduceLaunch R;
+    R.ndim = 2;
+    R.dtype = b->dtype;
+    R.order = d.order;
+    R.bc = d.bc;
+    R.n[0] = d.dims[0];
+    R.n[1] = d.dims[1];
+    R.n[2] = 1;
+    const size_t esz = b->dtype == NLSE_F32 ? 8 : 16;
+    R.psi = static_cast<char*>(b->psi) + (size_t)d.psi_offset * esz;
+    R.V = d.v_offset >= 0 ? static_cast<const char*>(b->vpool) + (size_t)d.v_offset * (esz / 2) : nullptr;
+    R.a = d.a;
+    R.s = d.s;
+    R.h = d.h;
+    R.partials = reinterpret_cast<double*>(b->work + b->lay.partials);
+    R.out = out + 3 * j;
+    hipError_t e = nlse_launch_reduce(R, b->stream);
+    if (e != hipSuccess) return nlse_hip_fail(e, "reduction launch");
+  }
+  std::vector<double> host((size_t)b->nsims * 3);
+  hipError_t e = hipMemcpyAsync(host.data(), out, host.size() * sizeof(double), hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return nlse_hip_fail(e, "copying the reductions");
+  bool finite = true;
+  for (int j = 0; j < b->nsims; ++j) {
+    const double h2 = b->desc[j].h * b->desc[j].h;
+    mass[j] = h2 * host[3 * j];
+    energy[j] = h2 * (host[3 * j + 1] + host[3 * j + 2]);
+    finite = finite && std::isfinite(mass[j]) && std::isfinite(energy[j]);
+  }
+  return finite ? NLSE_OK : nlse_fail(NLSE_EUNSTABLE, "a problem has non-finite mass or energy");
+}
+
+extern "C" int nlse_batch_status(nlse_batch* b) {
+  if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
+  unsigned flag[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(flag, b->work + b->lay.barrier, sizeof flag, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return nlse_hip_fail(e, "reading the batch status");
+  return flag[1] ? nlse_fail(NLSE_EDEVICE, "a grid-wide barrier of the batched kernel timed out") : NLSE_OK;
+}
+
+extern "C" int nlse_batch_info(const nlse_batch* b, int64_t info[4]) {
+  if (!b || !info) return nlse_fail(NLSE_EINVAL, "NULL argument");
+  info[0] = b->nchunks;
+  info[1] = b->nitems;
+  info[2] = b->total_pts;
+  info[3] = (int64_t)b->graphs.size();
+  return NLSE_OK;
+}
+
+extern "C" int nlse_batch_destroy(nlse_batch* b) {
+  if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
+  destroy_graphs(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  delete b;
+  return NLSE_OK;
+}

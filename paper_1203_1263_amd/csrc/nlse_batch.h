@@ -1,0 +1,46 @@
+// Internal structures of the batched persistent integrator (batch.hip and
+// api_batch.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nlse {
+
+constexpr int kBatchTX = 32, kBatchTY = 8;  // tile of the batched kernel
+
+// One problem of a batch as the device sees it.  The physical constants are
+// the exact double values the single-grid path converts to the element type,
+// so a problem computes the same bits alone or inside a batch.
+struct BatchSim {
+  int nx, ny, order, bc;
+  int64_t psi_off;  // complex elements into the caller's field pool
+  int64_t v_off;    // real elements into the caller's potential pool, -1 = V == 0
+  int64_t woff;     // complex elements into the work pools
+  double a, s, inv_a, inv_h2, inv_6h2;
+  double dt, dt2, dt3, dt6;
+};
+
+struct BatchItem {
+  int sim;
+  int tx, ty;
+  int pad;
+};
+
+struct BatchLaunch {
+  int dtype, comp, nsteps, nchunks;
+  const BatchSim* sims;
+  const BatchItem* items;
+  const int* chunk_off;
+  void* psi;
+  const void* vpool;
+  const void* vzero;
+  void *acc, *bufA, *bufB, *lo;
+  unsigned* barrier;
+  unsigned spin_limit;
+};
+
+}  // namespace nlse
+
+hipError_t nlse_launch_batch(const nlse::BatchLaunch& L, hipStream_t st);
+hipError_t nlse_batch_occupancy(int dtype, int comp, int* blocks_per_cu);

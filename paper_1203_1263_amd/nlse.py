@@ -28,8 +28,17 @@ NLSE_F32, NLSE_F64 = 0, 1
 NLSE_CD2, NLSE_2SHOC = 2, 4
 NLSE_BC_DIRICHLET, NLSE_BC_MSD = 0, 1
 NLSE_COMPENSATED = 0x1
+NLSE_NO_GRAPH = 0x2
 
 BC = {"dirichlet": NLSE_BC_DIRICHLET, "msd": NLSE_BC_MSD}
+
+
+class SimDesc(ctypes.Structure):
+    """nlse_sim_desc of include/nlse.h."""
+    _fields_ = [("ndim", ctypes.c_int), ("dims", ctypes.c_int64 * 3), ("h", ctypes.c_double),
+                ("a", ctypes.c_double), ("s", ctypes.c_double), ("dt", ctypes.c_double),
+                ("order", ctypes.c_int), ("bc", ctypes.c_int), ("psi_offset", ctypes.c_int64),
+                ("v_offset", ctypes.c_int64)]
 
 
 class NLSEError(RuntimeError):
@@ -70,6 +79,16 @@ def load_library() -> ctypes.CDLL:
         "nlse_get_tile": (ctypes.c_int, [vp, ctypes.c_int, ip]),
         "nlse_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ip]),
         "nlse_destroy_grid": (ctypes.c_int, [vp]),
+        "nlse_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(SimDesc), ctypes.c_int,
+                                                      ctypes.c_uint, ctypes.POINTER(ctypes.c_size_t)]),
+        "nlse_batch_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(SimDesc),
+                                             ctypes.c_int, ctypes.c_uint, vp, ctypes.c_size_t, vp,
+                                             ctypes.c_size_t, vp, ctypes.c_size_t, vp]),
+        "nlse_batch_step_rk4": (ctypes.c_int, [vp, ctypes.c_int64]),
+        "nlse_batch_mass_energy": (ctypes.c_int, [vp, dp, dp]),
+        "nlse_batch_status": (ctypes.c_int, [vp]),
+        "nlse_batch_info": (ctypes.c_int, [vp, i64p]),
+        "nlse_batch_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -157,7 +176,50 @@ def nlse_destroy_grid(g):
     _check(load_library().nlse_destroy_grid(g), "nlse_destroy_grid")
 
 
-# ---------------------------------------------------------------- convenience object
+def nlse_batch_workspace_bytes(descs, dtype: int, flags: int = 0) -> int:
+    arr = (SimDesc * len(descs))(*descs)
+    out = ctypes.c_size_t(0)
+    _check(load_library().nlse_batch_workspace_bytes(len(descs), arr, dtype, flags, ctypes.byref(out)),
+           "nlse_batch_workspace_bytes")
+    return out.value
+
+
+def nlse_batch_create(descs, dtype, flags, psi_ptr, psi_elems, v_ptr, v_elems, work_ptr, work_bytes,
+                      stream_ptr):
+    arr = (SimDesc * len(descs))(*descs)
+    b = ctypes.c_void_p()
+    _check(load_library().nlse_batch_create(ctypes.byref(b), len(descs), arr, dtype, flags, psi_ptr,
+                                            psi_elems, v_ptr, v_elems, work_ptr, work_bytes, stream_ptr),
+           "nlse_batch_create")
+    return b
+
+
+def nlse_batch_step_rk4(b, nsteps: int):
+    _check(load_library().nlse_batch_step_rk4(b, nsteps), "nlse_batch_step_rk4")
+
+
+def nlse_batch_mass_energy(b, nsims: int):
+    m = (ctypes.c_double * nsims)()
+    e = (ctypes.c_double * nsims)()
+    _check(load_library().nlse_batch_mass_energy(b, m, e), "nlse_batch_mass_energy")
+    return list(m), list(e)
+
+
+def nlse_batch_status(b):
+    _check(load_library().nlse_batch_status(b), "nlse_batch_status")
+
+
+def nlse_batch_info(b):
+    info = (ctypes.c_int64 * 4)()
+    _check(load_library().nlse_batch_info(b, info), "nlse_batch_info")
+    return {"workgroups": info[0], "items": info[1], "points": info[2], "graphs": info[3]}
+
+
+def nlse_batch_destroy(b):
+    _check(load_library().nlse_batch_destroy(b), "nlse_batch_destroy")
+
+
+# ---------------------------------------------------------------- convenience objects
 
 class Grid:
     """A field on the GPU plus the library grid that integrates it.
@@ -238,6 +300,91 @@ class Grid:
         if self._g:
             nlse_destroy_grid(self._g)
             self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent 2D problems advanced by one persistent launch.
+
+    ``problems``: sequence of objects with ``psi0`` (2D complex array),
+    ``h``, ``a``, ``s``, ``V`` (array or None), ``order``, ``bc`` and a time
+    step given by ``dts[j]``.  Fields live in one device pool (``self.pool``);
+    ``field(j)`` returns a view of problem j.
+    """
+
+    def __init__(self, problems, dts, dtype: str = "f32", compensated: bool = False,
+                 graph: bool = True, stream=None):
+        import numpy as np
+        import torch
+        load_library()
+        self.np_c = np.complex64 if dtype == "f32" else np.complex128
+        self.np_r = np.float32 if dtype == "f32" else np.float64
+        self.tc = torch.complex64 if dtype == "f32" else torch.complex128
+        self.tr = torch.float32 if dtype == "f32" else torch.float64
+        self.dtype = NLSE_F32 if dtype == "f32" else NLSE_F64
+        self.flags = (NLSE_COMPENSATED if compensated else 0) | (0 if graph else NLSE_NO_GRAPH)
+        self.shapes = []
+        descs = []
+        poff = voff = 0
+        vparts, pparts = [], []
+        for p, dt in zip(problems, dts):
+            psi0 = np.asarray(p.psi0)
+            if psi0.ndim != 2:
+                raise ValueError("batches hold 2D problems")
+            ny, nx = psi0.shape
+            d = SimDesc()
+            d.ndim = 2
+            d.dims[0], d.dims[1], d.dims[2] = nx, ny, 1
+            d.h, d.a, d.s, d.dt = float(p.h), float(p.a), float(p.s), float(dt)
+            d.order = int(p.order)
+            d.bc = BC[p.bc] if isinstance(p.bc, str) else int(p.bc)
+            d.psi_offset = poff
+            if p.V is not None:
+                d.v_offset = voff
+                vparts.append(np.asarray(p.V, dtype=self.np_r).ravel())
+                voff += nx * ny
+            else:
+                d.v_offset = -1
+            pparts.append(psi0.astype(self.np_c).ravel())
+            self.shapes.append((ny, nx, poff))
+            poff += nx * ny
+            descs.append(d)
+        self.descs = descs
+        self.pool = torch.from_numpy(np.concatenate(pparts)).cuda()
+        self.vpool = torch.from_numpy(np.concatenate(vparts)).cuda() if vparts else None
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = nlse_batch_workspace_bytes(descs, self.dtype, self.flags)
+        self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.pool.device)
+        wptr = self.work.data_ptr() + ((-self.work.data_ptr()) % 256)
+        self._b = nlse_batch_create(descs, self.dtype, self.flags, self.pool.data_ptr(), poff,
+                                    self.vpool.data_ptr() if self.vpool is not None else None,
+                                    voff, wptr, nbytes, self.stream.cuda_stream)
+
+    def field(self, j):
+        ny, nx, off = self.shapes[j]
+        return self.pool[off:off + nx * ny].view(ny, nx)
+
+    def step(self, nsteps: int):
+        nlse_batch_step_rk4(self._b, nsteps)
+
+    def mass_energy(self):
+        return nlse_batch_mass_energy(self._b, len(self.descs))
+
+    def status(self):
+        nlse_batch_status(self._b)
+
+    def info(self):
+        return nlse_batch_info(self._b)
+
+    def close(self):
+        if self._b:
+            nlse_batch_destroy(self._b)
+            self._b = None
 
     def __del__(self):
         try:

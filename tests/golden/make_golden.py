@@ -35,6 +35,36 @@ def problems():
     }
 
 
+C4_SAMPLE = 10  # problems of the 512-problem batch checked against the oracle
+
+
+def c4_subset():
+    """Seeded subset of the batch: the largest problem plus random others."""
+    probs = wl.batch2d()
+    g = np.random.Generator(np.random.PCG64(777))
+    big = int(np.argmax([p.npts for p in probs]))
+    others = [int(i) for i in g.choice(len(probs), size=C4_SAMPLE + 4, replace=False) if int(i) != big]
+    return probs, [big] + others[:C4_SAMPLE - 1]
+
+
+def make_c4(name="c4_batch2d_512x500"):
+    probs, sel = c4_subset()
+    out = {"sel": np.array(sel, dtype=np.int64)}
+    t0 = time.time()
+    for j in sel:
+        p = probs[j]
+        dt = p.dt_fraction * oracle.dt_max(2, p.order, p.h, p.a)
+        u = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, p.nsteps, V=p.V, order=p.order, bc=p.bc)
+        idx = sample_indices(p.psi0.shape, n_uniform=2048, n_bnd=128)
+        M, E = oracle.mass_energy(u, p.h, p.a, p.s, V=p.V, order=p.order, bc=p.bc)
+        out[f"idx{j}"] = idx
+        out[f"val{j}"] = u.reshape(-1)[idx]
+        out[f"dt{j}"] = np.float64(dt)
+        out[f"me{j}"] = np.array([M, E])
+    np.savez_compressed(os.path.join(HERE, name + ".npz"), **out)
+    print(f"{name}: {time.time() - t0:.1f}s for {len(sel)} problems", flush=True)
+
+
 def sample_indices(shape, n_uniform=4096, n_bnd=512, seed=4242):
     g = np.random.Generator(np.random.PCG64(seed))
     size = int(np.prod(shape))
@@ -74,6 +104,9 @@ def make(name, build):
 
 
 if __name__ == "__main__":
-    todo = sys.argv[1:] or list(problems())
+    todo = sys.argv[1:] or (list(problems()) + ["c4_batch2d_512x500"])
     for n in todo:
-        make(n, problems()[n])
+        if n == "c4_batch2d_512x500":
+            make_c4(n)
+        else:
+            make(n, problems()[n])

@@ -101,3 +101,40 @@ def test_null_grid_is_rejected(lib):
 def test_strerror(lib):
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.nlse_strerror(code)
+
+
+def _desc(**kw):
+    d = nlse.SimDesc()
+    d.ndim = kw.get("ndim", 2)
+    dims = kw.get("dims", (64, 64, 1))
+    d.dims[0], d.dims[1], d.dims[2] = dims
+    d.h, d.a, d.s, d.dt = kw.get("h", 0.25), kw.get("a", 1.0), kw.get("s", 1.0), kw.get("dt", 1e-3)
+    d.order, d.bc = kw.get("order", 4), kw.get("bc", 0)
+    d.psi_offset, d.v_offset = kw.get("psi_offset", 0), kw.get("v_offset", -1)
+    return d
+
+
+def test_batch_workspace_and_validation():
+    n = nlse.nlse_batch_workspace_bytes([_desc(), _desc(dims=(128, 64, 1), psi_offset=4096)], nlse.NLSE_F32)
+    assert n >= 3 * 8 * (4096 + 8192)
+    for bad, code in ((dict(ndim=3), nlse.NLSE_EUNSUPPORTED), (dict(dims=(2, 64, 1)), nlse.NLSE_EINVAL),
+                      (dict(order=3), nlse.NLSE_EINVAL), (dict(dt=0.0), nlse.NLSE_EINVAL),
+                      (dict(a=-1.0), nlse.NLSE_EINVAL), (dict(v_offset=-2), nlse.NLSE_EINVAL)):
+        with pytest.raises(nlse.NLSEError) as e:
+            nlse.nlse_batch_workspace_bytes([_desc(**bad)], nlse.NLSE_F32)
+        assert e.value.code == code
+    with pytest.raises(nlse.NLSEError) as e:
+        nlse.nlse_batch_workspace_bytes([_desc()], nlse.NLSE_F64, nlse.NLSE_COMPENSATED)
+    assert e.value.code == nlse.NLSE_EUNSUPPORTED
+
+
+def test_batch_create_checks_pools_before_launch():
+    with pytest.raises(nlse.NLSEError) as e:  # field outside the pool
+        nlse.nlse_batch_create([_desc()], nlse.NLSE_F32, 0, 4096, 100, None, 0, 8192, 1 << 30, None)
+    assert e.value.code == nlse.NLSE_EINVAL
+    with pytest.raises(nlse.NLSEError) as e:  # potential offset without a pool
+        nlse.nlse_batch_create([_desc(v_offset=0)], nlse.NLSE_F32, 0, 4096, 4096, None, 0, 8192, 1 << 30, None)
+    assert e.value.code == nlse.NLSE_EINVAL
+    with pytest.raises(nlse.NLSEError) as e:  # workspace too small
+        nlse.nlse_batch_create([_desc()], nlse.NLSE_F32, 0, 4096, 4096, None, 0, 8192, 64, None)
+    assert e.value.code == nlse.NLSE_ENOMEM
