@@ -54,8 +54,11 @@ def parse():
     ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("TX", "TY", "CZ"),
                     help="stage tile (default: the library's default tile)")
     ap.add_argument("--autotune", action="store_true", help="let the autotuner pick the tile")
-    ap.add_argument("--workload", choices=["ring3d", "batch2d"], default="ring3d",
-                    help="ring3d: 3D GPE at n^3 (default); batch2d: 512 uneven 2D problems in one launch")
+    ap.add_argument("--workload", choices=["ring3d", "batch2d", "surrogate"], default="ring3d",
+                    help="ring3d: 3D GPE at n^3 (default); batch2d: 512 uneven 2D problems in one launch; "
+                         "surrogate: train the 16-step surrogate and time it against RK4")
+    ap.add_argument("--trajectories", type=int, default=200, help="surrogate: trajectories of 100 pairs")
+    ap.add_argument("--iters", type=int, default=3000, help="surrogate: Adam iterations")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -121,6 +124,22 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """Generate trajectories with the integrator, train the surrogate on them
+    with the library's kernels, and report its accuracy and its speedup over
+    16 RK4 steps at batch 1 and 64."""
+    from paper_1203_1263_amd import surrogate_train as st
+    res, _, _ = st.run(args.trajectories, args.iters)
+    hist = res.pop("loss_history")
+    out = {"metric": "surrogate speedup over 16 RK4 steps (2D 256^2 vortex fields)",
+           "value": res["speedup_b64"]["speedup"], "unit": "x", "n_gpus": 1, "steps": args.iters,
+           "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 (fp32 accumulate)", "data": "synthetic (trajectories of the FP32 2SHOC integrator)",
+           "config": {"workload": "surrogate_256^2_2shoc_msd", "trajectories": args.trajectories},
+           "surrogate": res, "loss_history_every_100": hist}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(problem, dt, steps_hint):
     """Time the FP64 oracle as it stands on a bounded sample of the workload."""
     import oracle
@@ -154,6 +173,9 @@ def main():
         return
     if args.workload == "batch2d":
         bench_batch(args)
+        return
+    if args.workload == "surrogate":
+        bench_surrogate(args)
         return
     import torch
     from paper_1203_1263_amd import workloads as wl

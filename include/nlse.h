@@ -205,6 +205,79 @@ int nlse_batch_info(const nlse_batch *b, int64_t info[4]);
 
 int nlse_batch_destroy(nlse_batch *b);
 
+/* ------------------------------------------------------------ surrogate */
+
+/* A learned surrogate of kSteps = 16 RK4 steps of 2D fields (FP32 complex,
+ * H x W, both multiples of 16): a 6-layer 3x3 convolutional residual network
+ * on the two real channels, 2 -> 48 -> 48 -> 48 -> 48 -> 48 -> 2, ReLU after
+ * layers 1-5, zero "same" padding, pred = psi + net(psi).  BF16 weights and
+ * activations, FP32 accumulation on the matrix cores, FP32 master weights.
+ * Not part of the paper's method: it is trained on trajectories of the
+ * integrator above, which stays its fallback and judge.
+ *
+ * Parameters: one FP32 device array of nlse_surrogate_param_count() values,
+ * per layer W (Cout, Cin, 3, 3) row-major then b (Cout), layers in order.
+ * It is borrowed; nlse_surrogate_train_step updates it in place. */
+typedef struct nlse_surrogate nlse_surrogate;
+
+int nlse_surrogate_param_count(void);
+
+/* Workspace for fields of H x W and batches up to max_batch (activations of
+ * every layer, gradients, Adam moments, reduction scratch). */
+int nlse_surrogate_workspace_bytes(int H, int W, int max_batch, size_t *bytes);
+
+/* h: grid spacing (for masses).  Converts the weights to the kernel layouts
+ * and zeroes the Adam moments (asynchronous on hip_stream). */
+int nlse_surrogate_create(nlse_surrogate **m, int H, int W, int max_batch,
+                          double h, float *params_dev, void *work_dev,
+                          size_t work_bytes, void *hip_stream);
+
+/* Call after the caller rewrote params_dev: rebuilds the BF16 weights and
+ * resets the optimiser. */
+int nlse_surrogate_refresh(nlse_surrogate *m);
+
+/* psi_out = psi_in + net(psi_in) for `batch` contiguous complex64 fields
+ * [batch][H][W]; psi_out must not alias psi_in. */
+int nlse_surrogate_forward(nlse_surrogate *m, const void *psi_in,
+                           void *psi_out, int batch);
+
+/* Loss = mean over fields, points and the 2 real channels of
+ * (pred - target)^2 and its gradient w.r.t. every parameter, written to
+ * grad_dev (FP32, parameter layout) or, if NULL, kept internally.  The weight
+ * gradient is summed in a fixed order (bitwise reproducible).  If loss is not
+ * NULL the call synchronises and returns the loss. */
+int nlse_surrogate_loss_grad(nlse_surrogate *m, const void *psi_in,
+                             const void *psi_target, int batch,
+                             float *grad_dev, double *loss);
+
+/* One Adam step (b1 = 0.9, b2 = 0.999, eps = 1e-8) on the loss above with
+ * learning rate lr; loss (pre-update) returned if not NULL (synchronises). */
+int nlse_surrogate_train_step(nlse_surrogate *m, const void *psi_in,
+                              const void *psi_target, int batch, float lr,
+                              double *loss);
+
+/* Masses h^2 sum |psi|^2 of `batch` fields into a host array (FP64, fixed
+ * order; synchronises). */
+int nlse_surrogate_field_mass(nlse_surrogate *m, const void *psi, int batch,
+                              double *mass);
+
+/* Boundary points of psi_out keep their phase and take the modulus of
+ * psi_in (the fixed modulus of the MSD condition, Eq. BCMSDdef). */
+int nlse_surrogate_project_msd(nlse_surrogate *m, const void *psi_in,
+                               void *psi_out, int batch);
+
+/* Advance a 2D FP32 grid (same H x W, same stream) by nblocks blocks of 16
+ * RK4 steps of size dt: each block is one surrogate evaluation (plus the MSD
+ * projection when bc is NLSE_BC_MSD); if the relative mass drift of the block
+ * exceeds drift_tol the block is discarded and recomputed by nlse_step_rk4
+ * (order, bc, dt, 16).  *n_fallbacks receives the number of such blocks.
+ * Synchronises once or twice per block. */
+int nlse_surrogate_advance(nlse_surrogate *m, nlse_grid *g, int order, int bc,
+                           double dt, int64_t nblocks, double drift_tol,
+                           int64_t *n_fallbacks);
+
+int nlse_surrogate_destroy(nlse_surrogate *m);
+
 #ifdef __cplusplus
 }
 #endif

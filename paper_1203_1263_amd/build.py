@@ -32,8 +32,8 @@ COMMON = [
     "-I", INCLUDE, "-I", CSRC,
 ]
 
-SOURCES = ["stage3d.hip", "stage2d.hip", "stage1d.hip", "stage.hip", "batch.hip", "reduce.hip", "api.cpp",
-           "api_batch.cpp"]
+SOURCES = ["stage3d.hip", "stage2d.hip", "stage1d.hip", "stage.hip", "batch.hip", "surrogate.hip", "reduce.hip",
+           "api.cpp", "api_batch.cpp", "api_surrogate.cpp"]
 
 
 def _compile(src: str) -> str:

@@ -125,6 +125,18 @@ struct nlse_grid {
   int tile[2][3];  // [0] CD2, [1] 2SHOC
 };
 
+// Read-only view of a grid for the other C-ABI translation units.
+void nlse_grid_view(const nlse_grid* g, int* ndim, int64_t n[3], int* dtype, unsigned* flags, double* h,
+                    void** psi, void** stream) {
+  *ndim = g->shape.ndim;
+  for (int d = 0; d < 3; ++d) n[d] = g->shape.n[d];
+  *dtype = g->dtype;
+  *flags = g->flags;
+  *h = g->h;
+  *psi = g->psi;
+  *stream = g->stream;
+}
+
 extern "C" double nlse_dt_max(int ndim, int order, double h, double a) {
   if (ndim < 1 || ndim > 3 || (order != 2 && order != 4) || !(h > 0) || !(a > 0) || !std::isfinite(h) ||
       !std::isfinite(a))

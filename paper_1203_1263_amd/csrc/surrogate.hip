@@ -1,0 +1,533 @@
+// Learned surrogate of 16 RK4 steps: a 6-layer 3x3 convolutional residual
+// network on the field's two real channels (2 -> 48 -> 48 -> 48 -> 48 -> 48
+// -> 2, ReLU after layers 1-5, zero "same" padding, pred = psi + net(psi)).
+// BF16 weights and activations, FP32 accumulation on the matrix cores
+// (v_mfma_f32_16x16x32_bf16), FP32 master weights and Adam.
+//
+// Activations are NHWC BF16 with the channel count padded to a multiple of 8
+// (input 2 -> 8, last-layer output 2 -> 16).  A 3x3 convolution is an implicit
+// GEMM: D[co][pixel] = sum_k W[co][k] X[k][pixel] with k = (tap, ci), tap =
+// 3 ky + kx.  A workgroup computes a 16x16 pixel tile for every output
+// channel: the weights ([co][tap][ci], K contiguous) and the input tile with a
+// one-pixel halo ([pixel][ci]) sit in LDS; each wave owns four pixel rows and
+// all channel blocks.  The backward data pass is the same kernel with flipped
+// taps and transposed channels, masked by the ReLU of the stored activation.
+// The weight gradient is a second MFMA kernel (pixels are the reduction
+// dimension) writing per-workgroup partials that a fixed-order pass sums, so
+// gradients are bitwise reproducible.
+#include <stdint.h>
+
+#include "nlse_device.hpp"
+#include "nlse_surrogate.h"
+
+namespace nlse {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ bf16x8 as_bf16x8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ float bf16_val(uint16_t b) { return (float)__builtin_bit_cast(__bf16, b); }
+
+// ---------------------------------------------------------------- packing
+
+// complex64 field [n] -> BF16 [n][8] = (re, im, 0, ..., 0)
+__global__ void pack_input_kernel(const float2* __restrict__ psi, uint4* __restrict__ x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float2 v = psi[i];
+    uint4 o;
+    o.x = (uint32_t)bf16_bits(v.x) | ((uint32_t)bf16_bits(v.y) << 16);
+    o.y = o.z = o.w = 0u;
+    x[i] = o;
+  }
+}
+
+// ---------------------------------------------------------------- conv
+
+struct ConvArgs {
+  const uint16_t* in;    // [B][H][W][CIN] BF16
+  const uint16_t* w;     // [COUT][9][CIN] BF16
+  const float* bias;     // [COUT] (forward) or null
+  uint16_t* out;         // [B][H][W][COUT] BF16 (relu / dgrad)
+  const float2* x;       // network input field (last layer)
+  float2* pred;          // prediction (last layer)
+  const uint16_t* mask;  // dgrad: activation whose sign gates the gradient, [B][H][W][COUT]
+  int H, W;
+};
+
+enum { kEpiRelu = 0, kEpiLast = 1, kEpiDgrad = 2 };
+
+template <int CIN, int COUT, int EPI>
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+  constexpr int K = 9 * CIN;
+  constexpr int KSTEPS = (K + 31) / 32;
+  constexpr int NCB = COUT / 16;
+  constexpr int CH = CIN / 8;  // 16-byte chunks per input pixel
+  __shared__ __attribute__((aligned(16))) uint16_t sIn[18 * 18 * CIN];
+  __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * K];
+
+  const int tid = threadIdx.x;
+  const int tilesx = a.W / 16, tilesy = a.H / 16;
+  const int t = blockIdx.x;
+  const int b = t / (tilesx * tilesy);
+  const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
+  const int x0 = tx * 16, y0 = ty * 16;
+  const int64_t img = (int64_t)b * a.H * a.W;
+
+  // weights -> LDS (16-byte chunks; COUT*K*2 is a multiple of 16)
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(a.w);
+    uint4* dst = reinterpret_cast<uint4*>(sW);
+    for (int i = tid; i < COUT * K / 8; i += 256) dst[i] = src[i];
+  }
+  // input tile with a one-pixel halo -> LDS, zero outside the image
+  {
+    uint4* dst = reinterpret_cast<uint4*>(sIn);
+    for (int i = tid; i < 18 * 18 * CH; i += 256) {
+      const int pp = i / CH, part = i - pp * CH;
+      const int py = pp / 18, px = pp - py * 18;
+      const int gy = y0 - 1 + py, gx = x0 - 1 + px;
+      uint4 v = zero4();
+      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+        v = reinterpret_cast<const uint4*>(a.in + (img + (int64_t)gy * a.W + gx) * CIN)[part];
+      dst[i] = v;
+    }
+  }
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, g = lane >> 4;
+  f32x4 acc[NCB][4];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 2
+  for (int ks = 0; ks < KSTEPS; ++ks) {
+    const int k0 = 32 * ks + 8 * g;
+    const bool kv = k0 < K;
+    const int tap = kv ? k0 / CIN : 0, ci0 = kv ? k0 % CIN : 0;
+    const int dy = tap / 3, dx = tap - 3 * dy;
+    bf16x8 af[NCB], bfr[4];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      af[cb] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * K + k0]) : zero4());
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int row = 4 * wave + rr;
+      bfr[rr] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sIn[((row + dy) * 18 + j + dx) * CIN + ci0]) : zero4());
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        acc[cb][rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cb], bfr[rr], acc[cb][rr], 0, 0, 0);
+  }
+
+  // lane holds D[co = 16 cb + 4 g + r][pixel (row, j)], r = 0..3
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int row = 4 * wave + rr;
+    const int64_t pix = img + (int64_t)(y0 + row) * a.W + (x0 + j);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int co = 16 * cb + 4 * g;
+      float v[4] = {acc[cb][rr][0], acc[cb][rr][1], acc[cb][rr][2], acc[cb][rr][3]};
+      if constexpr (EPI == kEpiRelu) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + a.bias[co + r], 0.f);
+      } else if constexpr (EPI == kEpiDgrad) {
+        const uint2 m = *reinterpret_cast<const uint2*>(a.mask + pix * COUT + co);
+        const uint16_t mb[4] = {(uint16_t)(m.x & 0xffffu), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffffu),
+                                (uint16_t)(m.y >> 16)};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = bf16_val(mb[r]) > 0.f ? v[r] : 0.f;
+      }
+      if constexpr (EPI == kEpiLast) {
+        if (g == 0) {  // channels 0, 1 are the real and imaginary increments
+          const float2 xv = a.x[pix];
+          a.pred[pix] = make_float2(xv.x + (v[0] + a.bias[0]), xv.y + (v[1] + a.bias[1]));
+        }
+      } else {
+        uint2 o;
+        o.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
+        o.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+        *reinterpret_cast<uint2*>(a.out + pix * COUT + co) = o;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- loss
+
+// d = pred - target; partial sums of |d|^2 per workgroup (FP64, fixed order);
+// dz6 = 2 d / nel as BF16 channels 0, 1 of a 16-channel gradient.
+__global__ __launch_bounds__(256) void loss_kernel(const float2* __restrict__ pred, const float2* __restrict__ tgt,
+                                                   uint16_t* __restrict__ dz, double* __restrict__ partial,
+                                                   int64_t n, float scale) {
+  __shared__ double red[4];
+  double s = 0.0;
+  const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const float2 p = pred[i], q = tgt[i];
+    const float dr = p.x - q.x, di = p.y - q.y;
+    s += (double)dr * dr + (double)di * di;
+    uint4 o0, o1;
+    o0.x = (uint32_t)bf16_bits(scale * dr) | ((uint32_t)bf16_bits(scale * di) << 16);
+    o0.y = o0.z = o0.w = 0u;
+    o1 = zero4();
+    uint4* d = reinterpret_cast<uint4*>(dz + i * 16);
+    d[0] = o0;
+    d[1] = o1;
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------- weight gradient
+
+struct WgradArgs {
+  const uint16_t* a;   // [B][H][W][CIN] layer input (BF16)
+  const uint16_t* dz;  // [B][H][W][COUT] gradient of the layer output (BF16)
+  float* partial;      // [gridDim.x][COUT][9*CIN + 1]: weight and bias partial sums
+  int B, H, W;
+};
+
+// dW[co][tap][ci] = sum_pixels dz[p][co] a[p + off(tap)][ci] and
+// db[co] = sum_pixels dz[p][co].  Tiles of 16 x 8 pixels; workgroup w takes
+// tiles w, w + G, w + 2G, ... in order, so each partial has a fixed order.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
+  constexpr int N = 9 * CIN;
+  constexpr int NB = (N + 15) / 16;
+  constexpr int MB = COUT / 16;
+  constexpr int NBLK = MB * NB;
+  constexpr int PER = (NBLK + 3) / 4;  // output blocks per wave
+  constexpr int CH = CIN / 8, CHZ = COUT / 8;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[3 * CIN * 10 * 16];  // [dx][ci][row][col]
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT * 128];          // [co][row][col]
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const int tilesx = A.W / 16, tilesy = A.H / 8;
+  const int ntiles = A.B * tilesx * tilesy;
+  f32x4 acc[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.f;  // bias partial of channel tid (tid < COUT)
+
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int b = t / (tilesx * tilesy);
+    const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
+    const int x0 = tx * 16, y0 = ty * 8;
+    const int64_t img = (int64_t)b * A.H * A.W;
+    __syncthreads();  // previous tile's LDS reads are done
+    // input halo tile (10 rows x 18 cols) -> three x-shifted channel-major copies
+    for (int i = tid; i < 10 * 18 * CH; i += 256) {
+      const int pp = i / CH, part = i - pp * CH;
+      const int r = pp / 18, c = pp - r * 18;
+      const int gy = y0 - 1 + r, gx = x0 - 1 + c;
+      uint4 v = zero4();
+      if (gy >= 0 && gy < A.H && gx >= 0 && gx < A.W)
+        v = reinterpret_cast<const uint4*>(A.a + (img + (int64_t)gy * A.W + gx) * CIN)[part];
+      const uint16_t e[8] = {(uint16_t)(v.x & 0xffffu), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffffu),
+                             (uint16_t)(v.y >> 16), (uint16_t)(v.z & 0xffffu), (uint16_t)(v.z >> 16),
+                             (uint16_t)(v.w & 0xffffu), (uint16_t)(v.w >> 16)};
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int cc = c - dx;
+        if (cc < 0 || cc >= 16) continue;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sA[((dx * CIN + part * 8 + q) * 10 + r) * 16 + cc] = e[q];
+      }
+    }
+    // output-gradient tile (8 rows x 16 cols) -> channel-major
+    for (int i = tid; i < 128 * CHZ; i += 256) {
+      const int pp = i / CHZ, part = i - pp * CHZ;
+      const int r = pp / 16, c = pp - r * 16;
+      const uint4 v = reinterpret_cast<const uint4*>(A.dz + (img + (int64_t)(y0 + r) * A.W + x0 + c) * COUT)[part];
+      const uint16_t e[8] = {(uint16_t)(v.x & 0xffffu), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffffu),
+                             (uint16_t)(v.y >> 16), (uint16_t)(v.z & 0xffffu), (uint16_t)(v.z >> 16),
+                             (uint16_t)(v.w & 0xffffu), (uint16_t)(v.w >> 16)};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sZ[(part * 8 + q) * 128 + pp] = e[q];
+    }
+    __syncthreads();
+    if (tid < COUT) {
+      float s = 0.f;
+      for (int p = 0; p < 128; ++p) s += bf16_val(sZ[tid * 128 + p]);
+      bacc += s;
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int p0 = 32 * ks + 8 * g;  // 8 consecutive pixels in one row
+      const int py = p0 >> 4, px = p0 & 15;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int blk = wave + 4 * q;
+        if (blk >= NBLK) break;
+        const int mb = blk / NB, nb = blk - mb * NB;
+        const int co = 16 * mb + j;
+        const bf16x8 af = as_bf16x8(*reinterpret_cast<const uint4*>(&sZ[co * 128 + p0]));
+        const int n = 16 * nb + j;
+        uint4 bv = zero4();
+        if (n < N) {
+          const int tap = n / CIN, ci = n - tap * CIN;
+          const int dy = tap / 3, dx = tap - 3 * dy;
+          bv = *reinterpret_cast<const uint4*>(&sA[((dx * CIN + ci) * 10 + py + dy) * 16 + px]);
+        }
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, as_bf16x8(bv), acc[q], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds D[co = 16 mb + 4 g + r][n = 16 nb + j]
+  float* P = A.partial + (int64_t)blockIdx.x * COUT * (N + 1);
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int blk = wave + 4 * q;
+    if (blk >= NBLK) break;
+    const int mb = blk / NB, nb = blk - mb * NB;
+    const int n = 16 * nb + j;
+    if (n < N)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) P[(16 * mb + 4 * g + r) * (N + 1) + n] = acc[q][r];
+  }
+  if (tid < COUT) P[tid * (N + 1) + N] = bacc;
+}
+
+// Fixed-order sum of the partials into the canonical gradient of one layer:
+// W (Cout, Cin, 3, 3) then b (Cout), real channels only.
+__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int nparts, int coutp, int cinp, int cout,
+                                    int cin, float* __restrict__ gw, float* __restrict__ gb) {
+  const int N = 9 * cinp;
+  const int total = cout * (9 * cin + 1);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+    int co, col;
+    const bool is_b = e >= cout * 9 * cin;
+    if (is_b) {
+      co = e - cout * 9 * cin;
+      col = N;
+    } else {
+      co = e / (9 * cin);
+      const int rem = e - co * 9 * cin;  // (ci, ky, kx)
+      const int ci = rem / 9, tap = rem - ci * 9;
+      col = tap * cinp + ci;
+    }
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += (double)partial[((int64_t)p * coutp + co) * (N + 1) + col];
+    if (is_b)
+      gb[co] = (float)s;
+    else
+      gw[e] = (float)s;
+  }
+}
+
+// ---------------------------------------------------------------- weights, optimiser
+
+// Canonical FP32 layer (W (cout, cin, 3, 3), b) -> BF16 kernel layouts:
+// forward [coutp][tap][cinp]; backward-data [cinp][tap'][coutp] with tap'
+// the point-reflected tap (8 - tap).  Padded entries are zero.
+__global__ void prep_weights_kernel(const float* __restrict__ w, int cout, int cin, int coutp, int cinp,
+                                    uint16_t* __restrict__ fwd, uint16_t* __restrict__ bwd) {
+  const int nf = coutp * 9 * cinp;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
+    // forward
+    {
+      const int co = e / (9 * cinp), rem = e - co * 9 * cinp;
+      const int tap = rem / cinp, ci = rem - tap * cinp;
+      const float v = (co < cout && ci < cin) ? w[(co * cin + ci) * 9 + tap] : 0.f;
+      fwd[e] = bf16_bits(v);
+    }
+    if (bwd) {
+      const int ci = e / (9 * coutp), rem = e - ci * 9 * coutp;
+      const int tp = rem / coutp, co = rem - tp * coutp;
+      const int tap = 8 - tp;
+      const float v = (co < cout && ci < cin) ? w[(co * cin + ci) * 9 + tap] : 0.f;
+      bwd[e] = bf16_bits(v);
+    }
+  }
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+// p -= lr mhat / (sqrt(vhat) + eps) with bias corrections c1 = 1 - b1^t, c2 = 1 - b2^t.
+__global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int n, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------- checks
+
+// Per-field mass h^2 sum |psi|^2 of B fields of n points: workgroup (f, c)
+// reduces a fixed chunk in FP64; then a fixed-order pass per field.
+__global__ __launch_bounds__(256) void field_mass_partial_kernel(const float2* __restrict__ psi, int64_t n,
+                                                                 int chunks, double* __restrict__ partial) {
+  __shared__ double red[4];
+  const int f = blockIdx.x / chunks, c = blockIdx.x - f * chunks;
+  const int64_t len = (n + chunks - 1) / chunks;
+  const int64_t i0 = (int64_t)c * len, i1 = min(n, i0 + len);
+  const float2* P = psi + (int64_t)f * n;
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+    const float2 v = P[i];
+    s += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void field_mass_final_kernel(const double* __restrict__ partial, int fields, int chunks, double h2,
+                                        double* __restrict__ out) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= fields) return;
+  double s = 0.0;
+  for (int c = 0; c < chunks; ++c) s += partial[f * chunks + c];
+  out[f] = h2 * s;
+}
+
+// MSD boundary projection: boundary points of the prediction keep their
+// phase and take the modulus of the input (|psi_b|^2 is the fixed value of
+// the modulus-squared Dirichlet condition, Eq. BCMSDdef).
+__global__ void msd_project_kernel(const float2* __restrict__ in, float2* __restrict__ out, int B, int H, int W) {
+  const int per = 2 * W + 2 * (H - 2);
+  const int64_t total = (int64_t)B * per;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int b = (int)(e / per);
+    int k = (int)(e - (int64_t)b * per), y, x;
+    if (k < W) {
+      y = 0;
+      x = k;
+    } else if (k < 2 * W) {
+      y = H - 1;
+      x = k - W;
+    } else {
+      k -= 2 * W;
+      y = 1 + (k >> 1);
+      x = (k & 1) ? W - 1 : 0;
+    }
+    const int64_t i = (int64_t)b * H * W + (int64_t)y * W + x;
+    const float2 pi = in[i], po = out[i];
+    const float mi = sqrtf(pi.x * pi.x + pi.y * pi.y), mo = sqrtf(po.x * po.x + po.y * po.y);
+    if (mo > 0.f) out[i] = make_float2(po.x * (mi / mo), po.y * (mi / mo));
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+}  // namespace nlse
+
+using namespace nlse;
+
+hipError_t sg_pack_input(const void* psi, void* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float2*>(psi),
+                     static_cast<uint4*>(x), n);
+  return hipGetLastError();
+}
+
+hipError_t sg_conv(int kind, const SgConv& c, hipStream_t st) {
+  ConvArgs a;
+  a.in = c.in;
+  a.w = c.w;
+  a.bias = c.bias;
+  a.out = c.out;
+  a.x = static_cast<const float2*>(c.x);
+  a.pred = static_cast<float2*>(c.pred);
+  a.mask = c.mask;
+  a.H = c.H;
+  a.W = c.W;
+  const dim3 grid((unsigned)(c.B * (c.H / 16) * (c.W / 16)));
+  switch (kind) {
+    case kSgFirst: hipLaunchKernelGGL((conv3x3_kernel<8, 48, kEpiRelu>), grid, dim3(256), 0, st, a); break;
+    case kSgHidden: hipLaunchKernelGGL((conv3x3_kernel<48, 48, kEpiRelu>), grid, dim3(256), 0, st, a); break;
+    case kSgLast: hipLaunchKernelGGL((conv3x3_kernel<48, 16, kEpiLast>), grid, dim3(256), 0, st, a); break;
+    case kSgDgradLast: hipLaunchKernelGGL((conv3x3_kernel<16, 48, kEpiDgrad>), grid, dim3(256), 0, st, a); break;
+    case kSgDgradHidden: hipLaunchKernelGGL((conv3x3_kernel<48, 48, kEpiDgrad>), grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t sg_loss(const void* pred, const void* tgt, uint16_t* dz, double* partial, int nparts, int64_t n,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(loss_kernel, dim3(nparts), dim3(256), 0, st, static_cast<const float2*>(pred),
+                     static_cast<const float2*>(tgt), dz, partial, n, (float)(2.0 / (2.0 * (double)n)));
+  return hipGetLastError();
+}
+
+hipError_t sg_wgrad(int kind, const uint16_t* a, const uint16_t* dz, float* partial, int nparts, int B, int H, int W,
+                    hipStream_t st) {
+  WgradArgs A;
+  A.a = a;
+  A.dz = dz;
+  A.partial = partial;
+  A.B = B;
+  A.H = H;
+  A.W = W;
+  switch (kind) {
+    case kSgFirst: hipLaunchKernelGGL((wgrad_kernel<8, 48>), dim3(nparts), dim3(256), 0, st, A); break;
+    case kSgHidden: hipLaunchKernelGGL((wgrad_kernel<48, 48>), dim3(nparts), dim3(256), 0, st, A); break;
+    case kSgLast: hipLaunchKernelGGL((wgrad_kernel<48, 16>), dim3(nparts), dim3(256), 0, st, A); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t sg_wgrad_reduce(const float* partial, int nparts, int coutp, int cinp, int cout, int cin, float* gw,
+                           float* gb, hipStream_t st) {
+  const int total = cout * (9 * cin + 1);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, st, partial, nparts, coutp, cinp,
+                     cout, cin, gw, gb);
+  return hipGetLastError();
+}
+
+hipError_t sg_prep_weights(const float* w, int cout, int cin, int coutp, int cinp, uint16_t* fwd, uint16_t* bwd,
+                           hipStream_t st) {
+  const int n = coutp * 9 * cinp;
+  hipLaunchKernelGGL(prep_weights_kernel, dim3((n + 255) / 256), dim3(256), 0, st, w, cout, cin, coutp, cinp, fwd,
+                     bwd);
+  return hipGetLastError();
+}
+
+hipError_t sg_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                   float c1, float c2, hipStream_t st) {
+  hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t sg_field_mass(const void* psi, int fields, int64_t n, double h2, double* partial, int chunks, double* out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(field_mass_partial_kernel, dim3(fields * chunks), dim3(256), 0, st,
+                     static_cast<const float2*>(psi), n, chunks, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(field_mass_final_kernel, dim3((fields + 255) / 256), dim3(256), 0, st, partial, fields, chunks,
+                     h2, out);
+  return hipGetLastError();
+}
+
+hipError_t sg_msd_project(const void* in, void* out, int B, int H, int W, hipStream_t st) {
+  const int64_t n = (int64_t)B * (2 * W + 2 * (H - 2));
+  hipLaunchKernelGGL(msd_project_kernel, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float2*>(in),
+                     static_cast<float2*>(out), B, H, W);
+  return hipGetLastError();
+}

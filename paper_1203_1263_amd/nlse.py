@@ -89,6 +89,20 @@ def load_library() -> ctypes.CDLL:
         "nlse_batch_status": (ctypes.c_int, [vp]),
         "nlse_batch_info": (ctypes.c_int, [vp, i64p]),
         "nlse_batch_destroy": (ctypes.c_int, [vp]),
+        "nlse_surrogate_param_count": (ctypes.c_int, []),
+        "nlse_surrogate_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                          ctypes.POINTER(ctypes.c_size_t)]),
+        "nlse_surrogate_create": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_double, vp, vp, ctypes.c_size_t, vp]),
+        "nlse_surrogate_refresh": (ctypes.c_int, [vp]),
+        "nlse_surrogate_forward": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "nlse_surrogate_loss_grad": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, vp, dp]),
+        "nlse_surrogate_train_step": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]),
+        "nlse_surrogate_field_mass": (ctypes.c_int, [vp, vp, ctypes.c_int, dp]),
+        "nlse_surrogate_project_msd": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "nlse_surrogate_advance": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                                  ctypes.c_int64, ctypes.c_double, i64p]),
+        "nlse_surrogate_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -217,6 +231,70 @@ def nlse_batch_info(b):
 
 def nlse_batch_destroy(b):
     _check(load_library().nlse_batch_destroy(b), "nlse_batch_destroy")
+
+
+def nlse_surrogate_param_count() -> int:
+    return load_library().nlse_surrogate_param_count()
+
+
+def nlse_surrogate_workspace_bytes(H: int, W: int, max_batch: int) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().nlse_surrogate_workspace_bytes(H, W, max_batch, ctypes.byref(out)),
+           "nlse_surrogate_workspace_bytes")
+    return out.value
+
+
+def nlse_surrogate_create(H, W, max_batch, h, params_ptr, work_ptr, work_bytes, stream_ptr):
+    m = ctypes.c_void_p()
+    _check(load_library().nlse_surrogate_create(ctypes.byref(m), H, W, max_batch, h, params_ptr, work_ptr,
+                                                work_bytes, stream_ptr), "nlse_surrogate_create")
+    return m
+
+
+def nlse_surrogate_refresh(m):
+    _check(load_library().nlse_surrogate_refresh(m), "nlse_surrogate_refresh")
+
+
+def nlse_surrogate_forward(m, psi_in_ptr, psi_out_ptr, batch):
+    _check(load_library().nlse_surrogate_forward(m, psi_in_ptr, psi_out_ptr, batch), "nlse_surrogate_forward")
+
+
+def nlse_surrogate_loss_grad(m, psi_in_ptr, tgt_ptr, batch, grad_ptr=None, want_loss=True):
+    loss = ctypes.c_double(0.0)
+    _check(load_library().nlse_surrogate_loss_grad(m, psi_in_ptr, tgt_ptr, batch, grad_ptr,
+                                                   ctypes.byref(loss) if want_loss else None),
+           "nlse_surrogate_loss_grad")
+    return loss.value
+
+
+def nlse_surrogate_train_step(m, psi_in_ptr, tgt_ptr, batch, lr, want_loss=True):
+    loss = ctypes.c_double(0.0)
+    _check(load_library().nlse_surrogate_train_step(m, psi_in_ptr, tgt_ptr, batch, lr,
+                                                    ctypes.byref(loss) if want_loss else None),
+           "nlse_surrogate_train_step")
+    return loss.value
+
+
+def nlse_surrogate_field_mass(m, psi_ptr, batch):
+    out = (ctypes.c_double * batch)()
+    _check(load_library().nlse_surrogate_field_mass(m, psi_ptr, batch, out), "nlse_surrogate_field_mass")
+    return list(out)
+
+
+def nlse_surrogate_project_msd(m, psi_in_ptr, psi_out_ptr, batch):
+    _check(load_library().nlse_surrogate_project_msd(m, psi_in_ptr, psi_out_ptr, batch),
+           "nlse_surrogate_project_msd")
+
+
+def nlse_surrogate_advance(m, g, order, bc, dt, nblocks, drift_tol):
+    nf = ctypes.c_int64(0)
+    _check(load_library().nlse_surrogate_advance(m, g, order, bc, dt, nblocks, drift_tol, ctypes.byref(nf)),
+           "nlse_surrogate_advance")
+    return nf.value
+
+
+def nlse_surrogate_destroy(m):
+    _check(load_library().nlse_surrogate_destroy(m), "nlse_surrogate_destroy")
 
 
 # ---------------------------------------------------------------- convenience objects
@@ -385,6 +463,82 @@ class Batch:
         if self._b:
             nlse_batch_destroy(self._b)
             self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Surrogate:
+    """The convolutional surrogate of 16 RK4 steps on H x W complex64 fields.
+
+    ``params`` is a float32 device tensor of ``nlse_surrogate_param_count()``
+    values (per layer W (Cout, Cin, 3, 3) then b); it is updated in place by
+    :meth:`train_step`.
+    """
+
+    def __init__(self, H: int, W: int, max_batch: int, h: float, params=None, stream=None):
+        import torch
+        load_library()
+        n = nlse_surrogate_param_count()
+        if params is None:
+            params = torch.zeros(n, dtype=torch.float32, device="cuda")
+        if params.dtype != torch.float32 or params.numel() != n or not params.is_cuda:
+            raise ValueError(f"params must be a float32 device tensor of {n} values")
+        self.params = params
+        self.H, self.W, self.max_batch = H, W, max_batch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = nlse_surrogate_workspace_bytes(H, W, max_batch)
+        self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=params.device)
+        wptr = self.work.data_ptr() + ((-self.work.data_ptr()) % 256)
+        self._m = nlse_surrogate_create(H, W, max_batch, h, params.data_ptr(), wptr, nbytes,
+                                        self.stream.cuda_stream)
+
+    def _check_fields(self, psi):
+        import torch
+        if psi.dtype != torch.complex64 or not psi.is_contiguous() or tuple(psi.shape[-2:]) != (self.H, self.W):
+            raise ValueError("fields must be contiguous complex64 [batch, H, W]")
+        return psi.shape[0] if psi.dim() == 3 else 1
+
+    def refresh(self):
+        nlse_surrogate_refresh(self._m)
+
+    def forward(self, psi, out=None):
+        import torch
+        b = self._check_fields(psi)
+        out = torch.empty_like(psi) if out is None else out
+        nlse_surrogate_forward(self._m, psi.data_ptr(), out.data_ptr(), b)
+        return out
+
+    def loss_grad(self, psi, target):
+        import torch
+        b = self._check_fields(psi)
+        grad = torch.empty_like(self.params)
+        loss = nlse_surrogate_loss_grad(self._m, psi.data_ptr(), target.data_ptr(), b, grad.data_ptr())
+        return loss, grad
+
+    def train_step(self, psi, target, lr: float, want_loss: bool = True):
+        b = self._check_fields(psi)
+        return nlse_surrogate_train_step(self._m, psi.data_ptr(), target.data_ptr(), b, lr, want_loss)
+
+    def field_mass(self, psi):
+        b = self._check_fields(psi)
+        return nlse_surrogate_field_mass(self._m, psi.data_ptr(), b)
+
+    def project_msd(self, psi_in, psi_out):
+        b = self._check_fields(psi_in)
+        nlse_surrogate_project_msd(self._m, psi_in.data_ptr(), psi_out.data_ptr(), b)
+
+    def advance(self, grid, order, bc, dt, nblocks, drift_tol):
+        return nlse_surrogate_advance(self._m, grid._g, order, BC[bc] if isinstance(bc, str) else bc, dt,
+                                      nblocks, drift_tol)
+
+    def close(self):
+        if self._m:
+            nlse_surrogate_destroy(self._m)
+            self._m = None
 
     def __del__(self):
         try:

@@ -93,9 +93,13 @@ def dark_soliton1d_exact(x, t, a=1.0, s=-1.0, c=0.5, om=-1.0):
 
 # ------------------------------------------------------------------ 2D vortices
 
-def _vortex_centres(g: np.random.Generator, nv: int, box: float, min_dist: float):
+def _vortex_centres(g: np.random.Generator, nv: int, box: float, min_dist: float, max_draws: int = 100000):
     pts: List[np.ndarray] = []
+    draws = 0
     while len(pts) < nv:
+        draws += 1
+        if draws > max_draws:
+            raise ValueError(f"cannot place {nv} centres {min_dist} apart in a box of half-width {box}")
         p = g.uniform(-box, box, size=2)
         if all(np.hypot(*(p - q)) >= min_dist for q in pts):
             pts.append(p)

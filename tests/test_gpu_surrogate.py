@@ -1,0 +1,169 @@
+"""GPU tests of the BF16-MFMA convolutional surrogate against the FP64 CPU
+reference.
+
+Tolerances.  Weights and activations are rounded to BF16 (unit roundoff
+u = 2^-8 = 3.9e-3) and products are accumulated in FP32.  The increment
+net(psi) passes through 6 layers, each adding a relative rounding of about
+u (activation) + u (weight); errors add roughly in quadrature over 6 layers:
+sqrt(12) u = 1.4e-2.  Forward increments are therefore checked at 3e-2
+relative L2 and gradients (two BF16 operands per product plus BF16 output
+gradients) at 5e-2 normwise per layer.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate as S
+from paper_1203_1263_amd import workloads as wl
+from gpu_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def fields(batch, H, W, seed):
+    """Central H x W crops of 256^2 vortex fields (the surrogate workload)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for b in range(batch):
+        f = wl.surrogate_ic(g, n=256, h=0.25)
+        y0, x0 = (256 - H) // 2, (256 - W) // 2
+        out.append(f[y0:y0 + H, x0:x0 + W])
+    return np.array(out)
+
+
+def make(H, W, batch, seed=11):
+    import torch
+    from paper_1203_1263_amd.nlse import Surrogate
+    p = S.init_params(seed)
+    flat = S.pack(p)
+    params = torch.from_numpy(flat.astype(np.float32)).cuda()
+    m = Surrogate(H, W, batch, 0.25, params=params)
+    # the reference uses the FP32-rounded parameters the GPU starts from
+    return m, S.unpack(flat.astype(np.float32).astype(np.float64)), params
+
+
+def test_forward_matches_reference():
+    import torch
+    H, W, B = 32, 48, 3
+    m, p, _ = make(H, W, B)
+    x = fields(B, H, W, 5)
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    pred = m.forward(xd).cpu().numpy().astype(np.complex128)
+    ref, _ = S.forward(p, x.astype(np.complex64).astype(np.complex128))
+    x64 = x.astype(np.complex64).astype(np.complex128)
+    err = rel_l2(pred - x64, ref - x64)
+    assert err < 3e-2, err
+    assert np.linalg.norm(ref - x64) > 1e-3 * np.linalg.norm(x64)  # the increment is not trivial
+
+
+def test_gradients_match_reference_and_are_reproducible():
+    import torch
+    H, W, B = 32, 32, 2
+    m, p, _ = make(H, W, B, seed=4)
+    x = fields(B, H, W, 6)
+    t = fields(B, H, W, 7) * 0.1 + x
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    td = torch.from_numpy(t.astype(np.complex64)).cuda()
+    loss, grad = m.loss_grad(xd, td)
+    loss2, grad2 = m.loss_grad(xd, td)
+    assert loss == loss2 and torch.equal(grad, grad2)
+    x64 = x.astype(np.complex64).astype(np.complex128)
+    t64 = t.astype(np.complex64).astype(np.complex128)
+    Lr, gr = S.loss_and_grad(p, x64, t64)
+    assert loss == pytest.approx(Lr, rel=2e-2)
+    g = S.unpack(grad.cpu().numpy().astype(np.float64))
+    for l, ((gw, gb), (rw, rb)) in enumerate(zip(g, gr)):
+        assert rel_l2(gw, rw) < 5e-2, f"layer {l + 1} weights: {rel_l2(gw, rw):.3e}"
+        assert rel_l2(gb, rb) < 5e-2, f"layer {l + 1} bias: {rel_l2(gb, rb):.3e}"
+
+
+def test_adam_step_matches_reference():
+    import torch
+    H, W, B = 16, 32, 2
+    m, p, params = make(H, W, B, seed=9)
+    x = fields(B, H, W, 8)
+    t = x * np.exp(-0.2j)
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    td = torch.from_numpy(t.astype(np.complex64)).cuda()
+    p0 = params.cpu().numpy().astype(np.float64)
+    _, grad = m.loss_grad(xd, td)
+    g = grad.cpu().numpy().astype(np.float64)
+    m.train_step(xd, td, 1e-3)
+    torch.cuda.synchronize()
+    p1 = params.cpu().numpy().astype(np.float64)
+    ref, _, _ = S.adam_step(p0, g, np.zeros_like(p0), np.zeros_like(p0), 1, 1e-3)
+    assert np.max(np.abs(p1 - ref)) < 1e-6
+
+
+def test_training_reduces_loss():
+    import torch
+    H, W, B = 32, 32, 4
+    m, _, _ = make(H, W, B, seed=2)
+    x = fields(B, H, W, 3)
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    td = torch.from_numpy((x * np.exp(-0.2j)).astype(np.complex64)).cuda()
+    losses = [m.train_step(xd, td, 3e-3) for _ in range(30)]
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_field_mass_and_msd_projection():
+    import torch
+    H, W, B = 32, 16, 3
+    m, _, _ = make(H, W, B)
+    x = fields(B, H, W, 12)
+    xd = torch.from_numpy(x.astype(np.complex64)).cuda()
+    ms = m.field_mass(xd)
+    x32 = x.astype(np.complex64).astype(np.complex128)
+    for b in range(B):
+        assert ms[b] == pytest.approx(0.25 ** 2 * np.sum(np.abs(x32[b]) ** 2), rel=1e-12)
+    y = xd * 1.7
+    m.project_msd(xd, y)
+    yy = y.cpu().numpy()
+    ring = np.zeros((H, W), bool)
+    ring[0, :] = ring[-1, :] = ring[:, 0] = ring[:, -1] = True
+    assert np.allclose(np.abs(yy[:, ring]), np.abs(x[:, ring]), rtol=1e-6)
+    assert np.allclose(yy[:, ~ring], 1.7 * x.astype(np.complex64)[:, ~ring], rtol=1e-6)
+
+
+def test_advance_with_zero_tolerance_is_pure_rk4():
+    """drift_tol = 0 rejects every surrogate block, so the result must equal
+    plain RK4 (16 steps per block) bit for bit."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    H = W = 32
+    m, _, _ = make(H, W, 1)
+    x = fields(1, H, W, 13)[0]
+    dt = 0.8 * oracle.dt_max(2, 4, 0.25, 1.0)
+    a = torch.from_numpy(x.astype(np.complex64)).cuda()
+    b = a.clone()
+    ga = Grid(a, 0.25, 1.0, -1.0)
+    gb = Grid(b, 0.25, 1.0, -1.0)
+    nf = m.advance(ga, 4, "msd", dt, 3, 0.0)
+    gb.step(dt, 48, order=4, bc="msd")
+    torch.cuda.synchronize()
+    assert nf == 3
+    assert torch.equal(a, b)
+
+
+def test_advance_with_large_tolerance_uses_the_network():
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    H = W = 32
+    m, _, _ = make(H, W, 1)
+    x = fields(1, H, W, 14)[0]
+    a = torch.from_numpy(x.astype(np.complex64)).cuda()
+    g = Grid(a, 0.25, 1.0, -1.0)
+    nf = m.advance(g, 4, "dirichlet", 0.01, 2, 1e9)
+    torch.cuda.synchronize()
+    ref = torch.from_numpy(x.astype(np.complex64)).cuda()
+    for _ in range(2):
+        ref = m.forward(ref.reshape(1, H, W)).reshape(H, W)
+    assert nf == 0
+    assert torch.equal(a, ref)
