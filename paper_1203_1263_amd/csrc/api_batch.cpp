@@ -23,7 +23,7 @@ constexpr unsigned kSpinLimit = 1u << 25; // bounded barrier wait (~1-2 s)
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BatchLayout {
-  size_t acc, bufA, bufB, lo, sims, items, chunks, barrier, zero, partials, out, total;
+  size_t acc, bufA, bufB, lo, items, chunks, barrier, zero, partials, out, total;
 };
 
 int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, int64_t* total_pts,
@@ -69,7 +69,6 @@ BatchLayout layout(int nsims, int dtype, unsigned flags, int64_t tot, int64_t ni
   L.bufA = off; off += field;
   L.bufB = off; off += field;
   L.lo = off; if (flags & NLSE_COMPENSATED) off += field;
-  L.sims = off; off += a256(sizeof(nlse::BatchSim) * (size_t)nsims);
   L.items = off; off += a256(sizeof(nlse::BatchItem) * (size_t)nitems);
   L.chunks = off; off += a256(sizeof(int) * (size_t)(kMaxChunks + 1));
   L.barrier = off; off += 256;
@@ -86,7 +85,6 @@ struct nlse_batch {
   int nsims, dtype;
   unsigned flags;
   std::vector<nlse_sim_desc> desc;
-  std::vector<nlse::BatchSim> sims;
   int64_t total_pts, nitems;
   int nchunks;
   void* psi;
@@ -117,7 +115,6 @@ static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
   L.comp = (b->flags & NLSE_COMPENSATED) ? 1 : 0;
   L.nsteps = (int)nsteps;
   L.nchunks = b->nchunks;
-  L.sims = reinterpret_cast<const nlse::BatchSim*>(b->work + b->lay.sims);
   L.items = reinterpret_cast<const nlse::BatchItem*>(b->work + b->lay.items);
   L.chunk_off = reinterpret_cast<const int*>(b->work + b->lay.chunks);
   L.psi = b->psi;
@@ -185,14 +182,14 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   B->cap = nullptr;
 
   // device descriptors: the same double constants the single-grid path uses
-  std::vector<nlse::BatchSim> ds(nsims);
   std::vector<nlse::BatchItem> it;
   std::vector<double> cost;
   it.reserve((size_t)items);
   int64_t woff = 0;
   for (int j = 0; j < nsims; ++j) {
     const nlse_sim_desc& d = sims[j];
-    nlse::BatchSim& s = ds[j];
+    nlse::BatchItem s;
+    std::memset(&s, 0, sizeof s);
     s.nx = (int)d.dims[0];
     s.ny = (int)d.dims[1];
     s.order = d.order;
@@ -210,15 +207,17 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
     s.dt2 = d.dt / 2.0;
     s.dt3 = d.dt / 3.0;
     s.dt6 = d.dt / 6.0;
+    s.sim = j;
     const int ntx = (s.nx + nlse::kBatchTX - 1) / nlse::kBatchTX, nty = (s.ny + nlse::kBatchTY - 1) / nlse::kBatchTY;
     const double c = (d.order == 4 ? 1.35 : 1.0) * (d.v_offset >= 0 ? 1.1 : 1.0);
     for (int ty = 0; ty < nty; ++ty)
       for (int tx = 0; tx < ntx; ++tx) {
-        it.push_back({j, tx, ty, 0});
+        s.tx = tx;
+        s.ty = ty;
+        it.push_back(s);
         cost.push_back(c);
       }
   }
-  B->sims = ds;
   // contiguous chunks of (problem, tile) items with balanced cost
   std::vector<int> chunk(B->nchunks + 1, (int)items);
   {
@@ -235,9 +234,7 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
     chunk[B->nchunks] = (int)items;
   }
   hipStream_t st = B->stream;
-  e = hipMemcpyAsync(B->work + L.sims, ds.data(), sizeof(nlse::BatchSim) * ds.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(B->work + L.items, it.data(), sizeof(nlse::BatchItem) * it.size(), hipMemcpyHostToDevice, st);
+  e = hipMemcpyAsync(B->work + L.items, it.data(), sizeof(nlse::BatchItem) * it.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(B->work + L.chunks, chunk.data(), sizeof(int) * chunk.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.zero, 256, st);

@@ -11,6 +11,16 @@
 // is a monotonically increasing arrival counter with a bounded wait: a wait
 // that exceeds the spin limit raises an error flag and every workgroup then
 // leaves the kernel, so the grid always drains.
+//
+// Within a stage the items of a chunk are software-pipelined: while item i
+// is computed, the loads of item i+1 are in flight in a second register set
+// and the descriptor of item i+2 in a third, so a workgroup never waits a
+// full memory round trip per item.  Descriptors are read with vector loads
+// (one dword per lane) and broadcast with readlane, which keeps their wait
+// separate from the LDS traffic of the item being computed.  Two LDS
+// buffers for the stage-input box alternate between consecutive items.
+#include <cstddef>
+
 #include "nlse_batch.h"
 #include "tile2d.hpp"
 
@@ -18,13 +28,12 @@ namespace nlse {
 
 template <typename T>
 struct BatchArgs {
-  const BatchSim* sims;
   const BatchItem* items;
   const int* chunk_off;  // items of chunk c: [chunk_off[c], chunk_off[c+1])
   cpx<T>* psi;           // caller's pool
   const T* vpool;        // caller's potential pool (may be null)
   const T* vzero;        // one zero element
-  cpx<T>* acc;           // work pools, indexed by BatchSim::woff
+  cpx<T>* acc;           // work pools, indexed by BatchItem::woff
   cpx<T>* bufA;
   cpx<T>* bufB;
   cpx<T>* lo;
@@ -63,73 +72,142 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, unsigned
   return ok != 0;
 }
 
-template <typename T, int STAGE>
-__device__ __forceinline__ StageArgs<T> sim_args(const BatchArgs<T>& B, const BatchSim& d) {
+// Dword k of the descriptor words held one per lane (lanes l and l + 32
+// hold dword l), broadcast to the whole wave.
+__device__ __forceinline__ int word_i32(unsigned w, int k) { return __builtin_amdgcn_readlane((int)w, k); }
+__device__ __forceinline__ int64_t word_i64(unsigned w, int k) {
+  return (int64_t)(((uint64_t)(unsigned)word_i32(w, k + 1) << 32) | (uint64_t)(unsigned)word_i32(w, k));
+}
+__device__ __forceinline__ double word_f64(unsigned w, int k) {
+  return __builtin_bit_cast(double, (uint64_t)word_i64(w, k));
+}
+#define NLSE_WORD(field) ((int)(offsetof(BatchItem, field) / 4))
+
+// The descriptor of item `it`, one dword per lane.
+__device__ __forceinline__ unsigned item_words(const BatchItem* items, int it) {
+  return reinterpret_cast<const unsigned*>(items + it)[threadIdx.x & 31];
+}
+
+template <typename T>
+struct ItemArgs {
   StageArgs<T> A;
-  cpx<T>* psi = B.psi + d.psi_off;
-  cpx<T>* a = B.bufA + d.woff;
-  cpx<T>* b = B.bufB + d.woff;
+  int order, bc, tx, ty;
+};
+
+// Stage arguments of one item, from its descriptor words.
+template <typename T, int STAGE>
+__device__ __forceinline__ ItemArgs<T> decode(const BatchArgs<T>& B, unsigned w) {
+  ItemArgs<T> I;
+  StageArgs<T>& A = I.A;
+  const int64_t psi_off = word_i64(w, NLSE_WORD(psi_off)), v_off = word_i64(w, NLSE_WORD(v_off));
+  const int64_t woff = word_i64(w, NLSE_WORD(woff));
+  cpx<T>* psi = B.psi + psi_off;
+  cpx<T>* a = B.bufA + woff;
+  cpx<T>* b = B.bufB + woff;
   A.uin = STAGE == 1 ? psi : (STAGE == 2 ? a : (STAGE == 3 ? b : a));
   A.uout = STAGE == 1 ? a : (STAGE == 2 ? b : (STAGE == 3 ? a : psi));
   A.psi = psi;
-  A.acc = B.acc + d.woff;
-  A.lo = B.lo ? B.lo + d.woff : nullptr;
-  A.V = d.v_off >= 0 ? B.vpool + d.v_off : B.vzero;
-  A.vs = d.v_off >= 0 ? 1 : 0;
-  A.nx = d.nx;
-  A.ny = d.ny;
+  A.acc = B.acc + woff;
+  A.lo = B.lo ? B.lo + woff : nullptr;
+  A.V = v_off >= 0 ? B.vpool + v_off : B.vzero;
+  A.vs = v_off >= 0 ? 1 : 0;
+  A.nx = word_i32(w, NLSE_WORD(nx));
+  A.ny = word_i32(w, NLSE_WORD(ny));
   A.nz = 1;
-  A.ph.a = (T)d.a;
-  A.ph.s = (T)d.s;
-  A.ph.inv_a = (T)d.inv_a;
-  A.ph.inv_h2 = (T)d.inv_h2;
-  A.ph.inv_6h2 = (T)d.inv_6h2;
-  const double ca = (STAGE == 1 || STAGE == 4) ? d.dt6 : d.dt3;
-  const double cn = STAGE == 3 ? d.dt : d.dt2;
+  A.ph.a = (T)word_f64(w, NLSE_WORD(a));
+  A.ph.s = (T)word_f64(w, NLSE_WORD(s));
+  A.ph.inv_a = (T)word_f64(w, NLSE_WORD(inv_a));
+  A.ph.inv_h2 = (T)word_f64(w, NLSE_WORD(inv_h2));
+  A.ph.inv_6h2 = (T)word_f64(w, NLSE_WORD(inv_6h2));
+  const double ca = (STAGE == 1 || STAGE == 4) ? word_f64(w, NLSE_WORD(dt6)) : word_f64(w, NLSE_WORD(dt3));
+  const double cn = STAGE == 3 ? word_f64(w, NLSE_WORD(dt)) : word_f64(w, NLSE_WORD(dt2));
   A.c_acc = (T)ca;
   A.c_next = (T)cn;
   A.c_acc_d = ca;
-  return A;
+  I.order = word_i32(w, NLSE_WORD(order));
+  I.bc = word_i32(w, NLSE_WORD(bc));
+  I.tx = word_i32(w, NLSE_WORD(tx));
+  I.ty = word_i32(w, NLSE_WORD(ty));
+  return I;
 }
+#undef NLSE_WORD
 
+template <typename T>
+struct BatchLds {
+  static constexpr int BSZ = (kBatchTX + 4) * (kBatchTY + 4);
+  cpx<T> u[2][BSZ];  // stage-input box, alternating between items
+  T v[2][BSZ];       // potential box, alternating between items
+  cpx<T> d[(kBatchTX + 2) * (kBatchTY + 2)];
+};
+
+// One stage over the items [i0, i1) of this workgroup's chunk.
 template <typename T, int STAGE, int COMP>
-__device__ __forceinline__ void run_item(const BatchArgs<T>& B, const BatchItem& w, cpx<T>* sU, cpx<T>* sD) {
-  const BatchSim d = B.sims[w.sim];
-  const StageArgs<T> A = sim_args<T, STAGE>(B, d);
-  if (d.order == 4) {
-    if (d.bc == kMSD)
-      tile2d<T, 4, kMSD, STAGE, COMP, kBatchTX, kBatchTY>(A, w.tx, w.ty, sU, sD);
+__device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i1, BatchLds<T>& S) {
+  constexpr int TX = kBatchTX, TY = kBatchTY;
+  using Regs = TileRegs<T, TX, TY>;
+  auto words = [&](int it) { return item_words(B.items, min(it, i1 - 1)); };
+  auto issue = [&](const ItemArgs<T>& I, Regs& r) {
+    if (I.order == 4)
+      tile2d_load<T, STAGE, COMP, TX, TY, 2>(I.A, I.tx, I.ty, r);
     else
-      tile2d<T, 4, kDirichlet, STAGE, COMP, kBatchTX, kBatchTY>(A, w.tx, w.ty, sU, sD);
-  } else {
-    if (d.bc == kMSD)
-      tile2d<T, 2, kMSD, STAGE, COMP, kBatchTX, kBatchTY>(A, w.tx, w.ty, sU, sD);
-    else
-      tile2d<T, 2, kDirichlet, STAGE, COMP, kBatchTX, kBatchTY>(A, w.tx, w.ty, sU, sD);
+      tile2d_load<T, STAGE, COMP, TX, TY, 1>(I.A, I.tx, I.ty, r);
+  };
+  auto compute = [&](const ItemArgs<T>& I, const Regs& r, int buf) {
+    cpx<T>* sU = S.u[buf];
+    T* sV = S.v[buf];
+    if (I.order == 4) {
+      if (I.bc == kMSD)
+        tile2d_compute<T, 4, kMSD, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+      else
+        tile2d_compute<T, 4, kDirichlet, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+    } else {
+      if (I.bc == kMSD)
+        tile2d_compute<T, 2, kMSD, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+      else
+        tile2d_compute<T, 2, kDirichlet, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+    }
+  };
+  // Item `it`: its loads are in flight in `cur`, its descriptor words (long
+  // arrived) are in `wcur` and the words of item it+1 are in flight in `wn`.
+  // Decode item it+1 and start its loads into `nxt`, start loading the words
+  // of item it+2 into `wnn`, then compute item it.  Decoded arguments are
+  // not carried between items (they would occupy some 30 scalar registers
+  // each); the words are decoded again where needed.  Past the end of the
+  // chunk the last item is loaded again (and not computed), which keeps the
+  // memory operations straight-line code.
+  auto body = [&](int it, const Regs& cur, Regs& nxt, unsigned& wcur, unsigned wn, unsigned& wnn, int buf) {
+    issue(decode<T, STAGE>(B, wn), nxt);
+    wnn = words(it + 2);
+    compute(decode<T, STAGE>(B, wcur), cur, buf);
+    wcur = wn;
+  };
+  if (i0 >= i1) return;
+  unsigned wcur = words(i0), wa = words(i0 + 1), wb;
+  Regs ra, rb;
+  issue(decode<T, STAGE>(B, wcur), ra);
+  int it = i0;
+  for (; it + 1 < i1; it += 2) {
+    body(it, ra, rb, wcur, wa, wb, 0);
+    body(it + 1, rb, ra, wcur, wb, wa, 1);
   }
+  if (it < i1) body(it, ra, rb, wcur, wa, wb, 0);
 }
 
 template <typename T, int COMP>
 __global__ __launch_bounds__(kBatchTX* kBatchTY) void batch2d_kernel(BatchArgs<T> B, int nsteps) {
-  __shared__ cpx<T> sU[(kBatchTY + 4) * (kBatchTX + 4)];
-  __shared__ cpx<T> sD[(kBatchTY + 2) * (kBatchTX + 2)];
+  __shared__ BatchLds<T> S;
   const int c = xcd_swizzle(blockIdx.x, gridDim.x);
   const int i0 = B.chunk_off[c], i1 = B.chunk_off[c + 1];
   unsigned k = 0;
   for (int n = 0; n < nsteps; ++n) {
-    for (int stage = 1; stage <= 4; ++stage) {
-      for (int it = i0; it < i1; ++it) {
-        const BatchItem w = B.items[it];
-        __syncthreads();  // the previous item's LDS reads are done
-        switch (stage) {
-          case 1: run_item<T, 1, COMP>(B, w, sU, sD); break;
-          case 2: run_item<T, 2, COMP>(B, w, sU, sD); break;
-          case 3: run_item<T, 3, COMP>(B, w, sU, sD); break;
-          default: run_item<T, 4, COMP>(B, w, sU, sD); break;
-        }
-      }
-      if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
-    }
+    batch_stage<T, 1, COMP>(B, i0, i1, S);
+    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    batch_stage<T, 2, COMP>(B, i0, i1, S);
+    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    batch_stage<T, 3, COMP>(B, i0, i1, S);
+    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    batch_stage<T, 4, COMP>(B, i0, i1, S);
+    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
   }
 }
 
@@ -141,7 +219,6 @@ static const void* kernel_ptr() {
 template <typename T, int COMP>
 static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
   BatchArgs<T> B;
-  B.sims = L.sims;
   B.items = L.items;
   B.chunk_off = L.chunk_off;
   B.psi = static_cast<cpx<T>*>(L.psi);

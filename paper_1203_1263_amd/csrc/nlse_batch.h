@@ -9,27 +9,24 @@ namespace nlse {
 
 constexpr int kBatchTX = 32, kBatchTY = 8;  // tile of the batched kernel
 
-// One problem of a batch as the device sees it.  The physical constants are
+// One work item (a tile of one problem) as the device sees it: 128 bytes,
+// read by the kernel as 32 dwords, one per lane.  The physical constants are
 // the exact double values the single-grid path converts to the element type,
 // so a problem computes the same bits alone or inside a batch.
-struct BatchSim {
-  int nx, ny, order, bc;
+struct BatchItem {
+  double a, s, inv_a, inv_h2, inv_6h2;
+  double dt, dt2, dt3, dt6;
   int64_t psi_off;  // complex elements into the caller's field pool
   int64_t v_off;    // real elements into the caller's potential pool, -1 = V == 0
   int64_t woff;     // complex elements into the work pools
-  double a, s, inv_a, inv_h2, inv_6h2;
-  double dt, dt2, dt3, dt6;
+  int nx, ny, order, bc;
+  int tx, ty;       // tile indices
+  int sim, pad;
 };
-
-struct BatchItem {
-  int sim;
-  int tx, ty;
-  int pad;
-};
+static_assert(sizeof(BatchItem) == 128, "BatchItem is read as 32 dwords");
 
 struct BatchLaunch {
   int dtype, comp, nsteps, nchunks;
-  const BatchSim* sims;
   const BatchItem* items;
   const int* chunk_off;
   void* psi;

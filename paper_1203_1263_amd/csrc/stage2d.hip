@@ -6,12 +6,10 @@ namespace nlse {
 
 template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY>
 __global__ __launch_bounds__(TX* TY) void stage2d_kernel(StageArgs<T> A) {
-  constexpr int H = ORDER == 4 ? 2 : 1;
-  __shared__ cpx<T> sU[(TY + 2 * H) * (TX + 2 * H)];
-  __shared__ cpx<T> sD[ORDER == 4 ? (TY + 2) * (TX + 2) : 1];
+  __shared__ TileLds<T, TX, TY, ORDER == 4 ? 2 : 1> S;
   const int ntx = (A.nx + TX - 1) / TX;
   const int t = xcd_swizzle(blockIdx.x, gridDim.x);
-  tile2d<T, ORDER, BC, STAGE, COMP, TX, TY>(A, t % ntx, t / ntx, sU, sD);
+  tile2d<T, ORDER, BC, STAGE, COMP, TX, TY>(A, t % ntx, t / ntx, S);
 }
 
 template <typename T, int O, int B, int S, int C>

@@ -22,6 +22,12 @@
 // needed for it; the boundary planes 0 and nz-1 reuse that F at z = 1 / nz-2.
 #include "stage_common.hpp"
 
+// Iterations of loads in flight: 1 (two register sets) or 2 (three sets,
+// one wave less occupancy at 32x8; measured slower at 256^3).
+#ifndef NLSE_3D_DEPTH
+#define NLSE_3D_DEPTH 1
+#endif
+
 namespace nlse {
 
 template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY>
@@ -33,6 +39,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   constexpr int NS = LOOK + 2;              // planes z-1 .. z+LOOK
   constexpr int DW = TX + 2, DH = TY + 2, DSZ = DW * DH;
   constexpr int PF = (BSZ + NT - 1) / NT;   // plane elements per thread
+  constexpr int DEPTH = NLSE_3D_DEPTH;      // planes of loads in flight
   __shared__ cpx<T> sU[NS * BSZ];
   __shared__ cpx<T> sD[ORDER == 4 ? 3 * DSZ : 1];
 
@@ -68,26 +75,46 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
 
   auto slot = [&](int z) -> cpx<T>* { return sU + (z % NS) * BSZ; };
   auto dslot = [&](int z) -> cpx<T>* { return sD + (z % 3) * DSZ; };
-  // element k of a plane box: clamped box index and clamped global offset
-  auto box_index = [&](int k) -> int { return min(tid + k * NT, BSZ - 1); };
-  auto box_goff = [&](int i) -> int64_t {
-    int rr = i / BW, cc = i - rr * BW;
-    int gx = min(max(x0 - H + cc, 0), nx - 1), gy = min(max(y0 - H + rr, 0), ny - 1);
-    return (int64_t)gy * nx + gx;
+  // 32-bit in-plane offsets; plane bases are uniform (scalar) pointers
+  const int c32 = (int)cidx, q32 = (int)qidx;
+  // the arrays of one plane, as uniform pointers
+  auto plane_args = [&](int z) -> StageArgs<T> {
+    StageArgs<T> P = A;
+    const int64_t o = (int64_t)z * ps;
+    P.uin += o;
+    P.psi += o;
+    P.acc += o;
+    P.uout += o;
+    if (COMP) P.lo += o;
+    P.V += o * P.vs;
+    return P;
   };
-  auto load_regs = [&](int z, cpx<T>(&r)[PF]) {
+  // per-thread constants of the stage-input plane box, hoisted out of the
+  // z loop: LDS index and clamped in-plane offset of each element it moves
+  int bidx[PF], boff[PF];
 #pragma unroll
-    for (int k = 0; k < PF; ++k) r[k] = A.uin[(int64_t)z * ps + box_goff(box_index(k))];
+  for (int k = 0; k < PF; ++k) {
+    const int i = min(tid + k * NT, BSZ - 1);
+    const int rr = i / BW, cc = i - rr * BW;
+    const int gx = min(max(x0 - H + cc, 0), nx - 1), gy = min(max(y0 - H + rr, 0), ny - 1);
+    bidx[k] = i;
+    boff[k] = gy * nx + gx;
+  }
+  auto load_regs = [&](int z, cpx<T>(&r)[PF]) {
+    const cpx<T>* P = A.uin + (int64_t)z * ps;
+#pragma unroll
+    for (int k = 0; k < PF; ++k) r[k] = P[boff[k]];
   };
   auto put_regs = [&](int z, const cpx<T>(&r)[PF]) {
     cpx<T>* s = slot(z);
 #pragma unroll
-    for (int k = 0; k < PF; ++k) s[box_index(k)] = r[k];
+    for (int k = 0; k < PF; ++k) s[bidx[k]] = r[k];
   };
   auto load_pipe = [&](int zplane, int zown, Pipe& p) {
     load_regs(zplane, p.r);
-    load_own<T, STAGE, COMP>(A, (int64_t)zown * ps + cidx, p.own);
-    p.vq = vload(A, (int64_t)zown * ps + qidx);
+    const StageArgs<T> Po = plane_args(zown);
+    load_own<T, STAGE, COMP>(Po, c32, p.own);
+    p.vq = vload(Po, q32);
   };
   // CD2 at stage-input position i of plane zp (z-neighbours from LDS too).
   auto cd2 = [&](int zp, int i) -> cpx<T> {
@@ -104,6 +131,26 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     add_diff(sr, si, Pm[i], u);
     return mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
   };
+  // The D points (tile plus a one-cell ring) this thread computes on every
+  // plane, hoisted out of the z loop: LDS index, in-plane offsets of the point
+  // and of its in-plane MSD neighbour, and whether it is in the domain /
+  // interior in x and y.
+  constexpr int DPF = (DSZ + NT - 1) / NT;
+  int dbi[DPF], dqi[DPF], dgo[DPF], dgq[DPF];
+  bool din[DPF], dint[DPF];
+#pragma unroll
+  for (int k = 0; k < DPF; ++k) {
+    const int i = tid + k * NT;
+    const int r = i / DW, c = i - r * DW;
+    const int gx = x0 - 1 + c, gy = y0 - 1 + r;
+    din[k] = i < DSZ && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int qx = din[k] ? inward(gx, nx) : 0, qy = din[k] ? inward(gy, ny) : 0;
+    dint[k] = qx == 0 && qy == 0;
+    dbi[k] = (r + 1) * BW + c + 1;
+    dqi[k] = dbi[k] + qy * BW + qx;
+    dgo[k] = din[k] ? gy * nx + gx : 0;
+    dgq[k] = din[k] ? (gy + qy) * nx + gx + qx : 0;
+  }
   // D of plane zp on the tile plus a one-cell ring.  Interior points: CD2.
   // Boundary points: the Laplacian form of the boundary condition; on the
   // last plane every point is a boundary point, with its MSD neighbour in
@@ -111,27 +158,25 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   auto compute_D = [&](int zp) {
     cpx<T>* Dd = dslot(zp);
     const bool zbnd = (zp == nz - 1);
-    for (int i = tid; i < DSZ; i += NT) {
-      int r = i / DW, c = i - r * DW;
-      int gx = x0 - 1 + c, gy = y0 - 1 + r;
-      int bi = (r + 1) * BW + c + 1;
+#pragma unroll
+    for (int k = 0; k < DPF; ++k) {
+      const int i = tid + k * NT;
+      if (i >= DSZ) break;
       cpx<T> d = czero<T>();
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        int qx = inward(gx, nx), qy = inward(gy, ny);
-        if (!zbnd && qx == 0 && qy == 0) {
-          d = cd2(zp, bi);
+      if (din[k]) {
+        if (!zbnd && dint[k]) {
+          d = cd2(zp, dbi[k]);
         } else {
-          cpx<T> ub = slot(zp)[bi];
-          int64_t gi = (int64_t)zp * ps + (int64_t)gy * nx + gx;
-          T Nb = nlin(ph, ub, vload(A, gi));
+          const StageArgs<T> Pz = plane_args(zp);
+          cpx<T> ub = slot(zp)[dbi[k]];
+          T Nb = nlin(ph, ub, vload(Pz, dgo[k]));
           if (BC == kDirichlet) {
             d = dirichlet_lap(ph, ub, Nb);
           } else {
-            int qz = zbnd ? -1 : 0;
-            int qi = bi + qy * BW + qx;
-            cpx<T> uq = slot(zp + qz)[qi];
-            int64_t gq = gi + (int64_t)qz * ps + (int64_t)qy * nx + qx;
-            d = msd_lap(ph, cd2(zp + qz, qi), uq, nlin(ph, uq, vload(A, gq)), ub, Nb);
+            const int qz = zbnd ? -1 : 0;
+            const StageArgs<T> Pq = plane_args(zp + qz);
+            cpx<T> uq = slot(zp + qz)[dqi[k]];
+            d = msd_lap(ph, cd2(zp + qz, dqi[k]), uq, nlin(ph, uq, vload(Pq, dgq[k])), ub, Nb);
           }
         }
       }
@@ -150,8 +195,9 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   }
   cpx<T> um2 = czero<T>();
   if constexpr (ORDER == 4) um2 = A.uin[(int64_t)max(zb - 2, 0) * ps + qidx];
-  Pipe pa, pb;
+  Pipe pa, pb, pc;
   load_pipe(min(zb + LOOK, zmax), zb, pa);
+  if constexpr (DEPTH == 2) load_pipe(min(zb + 1 + LOOK, zmax), min(zb + 1, ze - 1), pb);
   __syncthreads();
 
   cpx<T> dm = czero<T>();  // D of plane z-1 at the q column
@@ -182,7 +228,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   }
 
   auto body = [&](int z, Pipe& cur, Pipe& nxt) {
-    load_pipe(min(z + 1 + LOOK, zmax), min(z + 1, ze - 1), nxt);
+    load_pipe(min(z + DEPTH + LOOK, zmax), min(z + DEPTH, ze - 1), nxt);
     __syncthreads();
     if constexpr (ORDER == 4) {
       if (z + 2 <= ze) compute_D(z + 2);
@@ -230,18 +276,18 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     const cpx<T> Kq = rhs(ph, L, uq, nlin(ph, uq, cur.vq));
     cpx<T> K = Kq;
     if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
-    if (store) stage_update<T, STAGE, COMP>(A, (int64_t)z * ps + cidx, u0, K, cur.own);
+    if (store) stage_update<T, STAGE, COMP>(plane_args(z), c32, u0, K, cur.own);
     // boundary planes: F_b from the interior neighbour in plane 1 / nz-2
     if (z == 1 || z == nz - 2) {
       for (int zz = 0; zz < 2; ++zz) {
         const int zbp = zz == 0 ? 0 : nz - 1;
         if ((zz == 0 && z != 1) || (zz == 1 && z != nz - 2)) continue;
-        const int64_t gi = (int64_t)zbp * ps + cidx;
+        const StageArgs<T> Pb = plane_args(zbp);
         Own<T> o;
-        load_own<T, STAGE, COMP>(A, gi, o);
+        load_own<T, STAGE, COMP>(Pb, c32, o);
         const cpx<T> ub = slot(zbp)[oi];
         const cpx<T> Kb = (BC == kMSD) ? msd_rhs(Kq, uq, ub) : czero<T>();
-        if (store) stage_update<T, STAGE, COMP>(A, gi, ub, Kb, o);
+        if (store) stage_update<T, STAGE, COMP>(Pb, c32, ub, Kb, o);
       }
     }
     if constexpr (ORDER == 4) dm = dslot(z)[di];
@@ -249,11 +295,21 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   };
 
   int z = zb;
-  for (; z + 1 < ze; z += 2) {
-    body(z, pa, pb);
-    body(z + 1, pb, pa);
+  if constexpr (DEPTH == 1) {
+    for (; z + 1 < ze; z += 2) {
+      body(z, pa, pb);
+      body(z + 1, pb, pa);
+    }
+    if (z < ze) body(z, pa, pb);
+  } else {
+    for (; z + 2 < ze; z += 3) {
+      body(z, pa, pc);
+      body(z + 1, pb, pa);
+      body(z + 2, pc, pb);
+    }
+    if (z < ze) body(z, pa, pc);
+    if (z + 1 < ze) body(z + 1, pb, pa);
   }
-  if (z < ze) body(z, pa, pb);
 }
 
 template <typename T, int O, int B, int S, int C>

@@ -29,6 +29,7 @@ from paper_1203_1263_amd import workloads as wl  # noqa: E402
 
 def problems():
     return {
+        "c2_vortex2d_1024x1024_1000": lambda: wl.vortex2d(n=1024, h=0.25, nsteps=1000),
         "c2_vortex2d_1024x1024_2000": lambda: wl.vortex2d(n=1024, h=0.25, nsteps=2000),
         "c3_ring3d_87x87x203_1000": lambda: wl.ring3d(shape=(203, 87, 87), h=0.14, nsteps=1000),
         "c3_ring3d_256x256x256_1000": lambda: wl.ring3d(shape=(256, 256, 256), h=0.1, nsteps=1000),
