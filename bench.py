@@ -38,7 +38,8 @@ BYTES_PER_PT_STEP = {"compensated": 168, "plain": 144}
 # (FETCH_SIZE scaled by 2.0, WRITE_SIZE by 1.0 against a plain 1 GiB copy) for
 # the compensated 256^3 run with tile (32, 8, 16); reported only for that
 # configuration.
-MEASURED_TRAFFIC = {("compensated", 256, (32, 8, 16)): 771.9e6}
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
+MEASURED_TRAFFIC = {("compensated", 256, (32, 8, 16)): 779.2e6}
 
 
 def parse():
@@ -136,6 +137,10 @@ def bench_surrogate(args):
            "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16 (fp32 accumulate)", "data": "synthetic (trajectories of the FP32 2SHOC integrator)",
            "config": {"workload": "surrogate_256^2_2shoc_msd", "trajectories": args.trajectories},
+           "roofline": {"bound": "mfma", "achieved": res["speedup_b64"]["forward_tflops"], "peak": BF16_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": res["speedup_b64"]["forward_tflops"] / BF16_PEAK_TFLOPS,
+                        "traffic": None,
+                        "kernel": f"surrogate forward (6 conv3x3 MFMA launches), batch {res['speedup_b64']['batch']}"},
            "surrogate": res, "loss_history_every_100": hist}
     print(json.dumps(out), flush=True)
 

@@ -168,29 +168,35 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
     }
   };
   // Item `it`: its loads are in flight in `cur`, its descriptor words (long
-  // arrived) are in `wcur` and the words of item it+1 are in flight in `wn`.
-  // Decode item it+1 and start its loads into `nxt`, start loading the words
-  // of item it+2 into `wnn`, then compute item it.  Decoded arguments are
-  // not carried between items (they would occupy some 30 scalar registers
-  // each); the words are decoded again where needed.  Past the end of the
-  // chunk the last item is loaded again (and not computed), which keeps the
-  // memory operations straight-line code.
-  auto body = [&](int it, const Regs& cur, Regs& nxt, unsigned& wcur, unsigned wn, unsigned& wnn, int buf) {
-    issue(decode<T, STAGE>(B, wn), nxt);
-    wnn = words(it + 2);
-    compute(decode<T, STAGE>(B, wcur), cur, buf);
-    wcur = wn;
+  // arrived) are in `wc`, the words of item it+1 are in flight in `wn`.
+  // Decode both items, reuse `wc` for the words of item it+2, start the
+  // loads of item it+1 into `nxt`, then compute item it.  The next item
+  // swaps the roles of (wc, wn) and (cur, nxt), so no register that a load
+  // is still writing is ever copied.  The scheduling barrier keeps the
+  // descriptor load ahead of the tile loads: waiting for it later must not
+  // mean waiting for them.  Past the end of the chunk the last item is
+  // loaded again (and not computed), which keeps the memory operations
+  // straight-line code.
+  auto body = [&](int it, const Regs& cur, Regs& nxt, unsigned& wc, unsigned wn, int buf) {
+    const ItemArgs<T> Icur = decode<T, STAGE>(B, wc);
+    const ItemArgs<T> Inxt = decode<T, STAGE>(B, wn);
+    wc = words(it + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    issue(Inxt, nxt);
+    compute(Icur, cur, buf);
   };
   if (i0 >= i1) return;
-  unsigned wcur = words(i0), wa = words(i0 + 1), wb;
+  unsigned wa = words(i0), wb = words(i0 + 1);
   Regs ra, rb;
-  issue(decode<T, STAGE>(B, wcur), ra);
+  const ItemArgs<T> I0 = decode<T, STAGE>(B, wa);
+  __builtin_amdgcn_sched_barrier(0);
+  issue(I0, ra);
   int it = i0;
   for (; it + 1 < i1; it += 2) {
-    body(it, ra, rb, wcur, wa, wb, 0);
-    body(it + 1, rb, ra, wcur, wb, wa, 1);
+    body(it, ra, rb, wa, wb, 0);      // wa <- words(it + 2)
+    body(it + 1, rb, ra, wb, wa, 1);  // wb <- words(it + 3)
   }
-  if (it < i1) body(it, ra, rb, wcur, wa, wb, 0);
+  if (it < i1) body(it, ra, rb, wa, wb, 0);
 }
 
 template <typename T, int COMP>

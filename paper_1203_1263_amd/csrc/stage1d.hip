@@ -47,7 +47,7 @@ __global__ __launch_bounds__(TX) void stage1d_kernel(StageArgs<T> A) {
       if (gx >= 0 && gx < nx) {
         cpx<T> c = sU[b];
         if (gx != 0 && gx != nx - 1) {
-          T sr = T(0), si = T(0);
+          T sr = T(-0.0), si = T(-0.0);
           add_diff(sr, si, sU[b + 1], c);
           add_diff(sr, si, sU[b - 1], c);
           d = mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
@@ -58,7 +58,7 @@ __global__ __launch_bounds__(TX) void stage1d_kernel(StageArgs<T> A) {
           } else {
             int q = inward(gx, nx);
             cpx<T> uq = sU[b + q];
-            T sr = T(0), si = T(0);
+            T sr = T(-0.0), si = T(-0.0);
             add_diff(sr, si, sU[b + q + 1], uq);
             add_diff(sr, si, sU[b + q - 1], uq);
             cpx<T> dq = mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
@@ -77,13 +77,13 @@ __global__ __launch_bounds__(TX) void stage1d_kernel(StageArgs<T> A) {
   if (valid) {
     cpx<T> L;
     if constexpr (ORDER == 2) {
-      T sr = T(0), si = T(0);
+      T sr = T(-0.0), si = T(-0.0);
       add_diff(sr, si, sU[qlx + H + 1], uq);
       add_diff(sr, si, sU[qlx + H - 1], uq);
       L = mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
     } else {
       cpx<T> D0 = sD[qlx + 1];
-      T fr = T(0), fi = T(0);
+      T fr = T(-0.0), fi = T(-0.0);
       add_diff(fr, fi, sD[qlx + 2], D0);
       add_diff(fr, fi, sD[qlx], D0);
       L = shoc_combine<T, 1>(ph, D0, fr, fi, T(0), T(0));

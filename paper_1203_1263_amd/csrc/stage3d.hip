@@ -122,7 +122,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     const cpx<T>* Pm = slot(zp - 1);
     const cpx<T>* Pp = slot(zp + 1);
     cpx<T> u = P[i];
-    T sr = T(0), si = T(0);
+    T sr = T(-0.0), si = T(-0.0);
     add_diff(sr, si, P[i + 1], u);
     add_diff(sr, si, P[i - 1], u);
     add_diff(sr, si, P[i + BW], u);
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     } else {
       const cpx<T>* P = slot(zb - 1);
       cpx<T> u = P[ci];
-      T sr = T(0), si = T(0);
+      T sr = T(-0.0), si = T(-0.0);
       add_diff(sr, si, P[ci + 1], u);
       add_diff(sr, si, P[ci - 1], u);
       add_diff(sr, si, P[ci + BW], u);
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     const cpx<T> uq = P0[ci];
     cpx<T> L;
     if constexpr (ORDER == 2) {
-      T sr = T(0), si = T(0);
+      T sr = T(-0.0), si = T(-0.0);
       add_diff(sr, si, P0[ci + 1], uq);
       add_diff(sr, si, P0[ci - 1], uq);
       add_diff(sr, si, P0[ci + BW], uq);
@@ -251,14 +251,14 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     } else {
       const cpx<T>* Dc = dslot(z);
       cpx<T> D0 = Dc[di];
-      T fr = T(0), fi = T(0);
+      T fr = T(-0.0), fi = T(-0.0);
       add_diff(fr, fi, Dc[di + 1], D0);
       add_diff(fr, fi, Dc[di - 1], D0);
       add_diff(fr, fi, Dc[di + DW], D0);
       add_diff(fr, fi, Dc[di - DW], D0);
       add_diff(fr, fi, dslot(z + 1)[di], D0);
       add_diff(fr, fi, dm, D0);
-      T er = T(0), ei = T(0);
+      T er = T(-0.0), ei = T(-0.0);
       add_diff(er, ei, P0[ci + BW + 1], uq);
       add_diff(er, ei, P0[ci + BW - 1], uq);
       add_diff(er, ei, P0[ci - BW + 1], uq);

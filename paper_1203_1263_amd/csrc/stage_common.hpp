@@ -22,6 +22,8 @@ __device__ __forceinline__ cpx<T> shoc_combine(const Phys<T>& p, cpx<T> D0, T fr
   return mk<T>(fmaT(c0, D0.re, fmaT(m12, fr, p.inv_6h2 * er)), fmaT(c0, D0.im, fmaT(m12, fi, p.inv_6h2 * ei)));
 }
 
+// Sums of differences start at -0: -0 + x == x exactly for every x, so the
+// compiler drops the first addition without fast-math.
 template <typename T>
 __device__ __forceinline__ void add_diff(T& sr, T& si, cpx<T> v, cpx<T> c) {
   sr += v.re - c.re;

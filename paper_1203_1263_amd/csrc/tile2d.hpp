@@ -106,7 +106,7 @@ __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, in
   auto Vb = [&](int r, int c) -> T { return sV[r * BW + c]; };
   auto cd2 = [&](int r, int c) -> cpx<T> {
     cpx<T> u = U(r, c);
-    T sr = T(0), si = T(0);
+    T sr = T(-0.0), si = T(-0.0);
     add_diff(sr, si, U(r, c + 1), u);
     add_diff(sr, si, U(r, c - 1), u);
     add_diff(sr, si, U(r + 1, c), u);
@@ -151,13 +151,13 @@ __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, in
       auto Dv = [&](int r, int c) -> cpx<T> { return sD[r * DW + c]; };
       const int r = qly + 1, c = qlx + 1;
       cpx<T> D0 = Dv(r, c);
-      T fr = T(0), fi = T(0);
+      T fr = T(-0.0), fi = T(-0.0);
       add_diff(fr, fi, Dv(r, c + 1), D0);
       add_diff(fr, fi, Dv(r, c - 1), D0);
       add_diff(fr, fi, Dv(r + 1, c), D0);
       add_diff(fr, fi, Dv(r - 1, c), D0);
       const int br = qly + H, bc = qlx + H;
-      T er = T(0), ei = T(0);
+      T er = T(-0.0), ei = T(-0.0);
       add_diff(er, ei, U(br + 1, bc + 1), uq);
       add_diff(er, ei, U(br + 1, bc - 1), uq);
       add_diff(er, ei, U(br - 1, bc + 1), uq);

@@ -35,6 +35,9 @@ from .nlse import Batch, Grid, Surrogate, nlse_dt_max
 
 N, H_STEP, A, S_NL = 256, 0.25, 1.0, -1.0
 BLOCK = 16
+# algorithmic flops of one forward pass per pixel: 2 per multiply-add over
+# the six 3x3 layers with their real channel counts (2-48-48-48-48-48-2)
+FLOP_PER_PIXEL = 2 * 9 * (2 * 48 + 4 * 48 * 48 + 48 * 2)
 
 
 class _P:
@@ -195,7 +198,10 @@ def speedup(m, snaps, batch: int):
             b.step(BLOCK)
     t_rk = _time(rk4_block, 10)
     t_sg = _time(surrogate_block, 10)
-    return {"batch": batch, "ms_rk4_16_steps": t_rk, "ms_surrogate_block": t_sg, "speedup": t_rk / t_sg}
+    t_fwd = _time(lambda: m.forward(fields, out), 10)
+    fwd_flop = FLOP_PER_PIXEL * batch * N * N
+    return {"batch": batch, "ms_rk4_16_steps": t_rk, "ms_surrogate_block": t_sg, "speedup": t_rk / t_sg,
+            "ms_forward": t_fwd, "forward_tflops": fwd_flop / (t_fwd * 1e-3) / 1e12}
 
 
 def run(ntraj: int = 200, iters: int = 3000, batch: int = 32, lr: float = 1e-3, seed: int = 0):
