@@ -42,21 +42,23 @@ struct BatchArgs {
 };
 
 // Grid-wide barrier number `k` (1, 2, ...): every workgroup adds one arrival
-// and waits for k * gridDim.x arrivals.  Device-scope release before the
-// arrival and acquire after it make the stage's stores visible to every
-// workgroup.  Returns false if the wait timed out or another workgroup
-// reported an error.
+// and waits for k * gridDim.x arrivals.  Only thread 0 crosses device scope:
+// the workgroup barrier first orders every wave's stores before thread 0's
+// agent-scope release (on this chip a release writes back the XCD's L2 and
+// an acquire invalidates it, so one of each per workgroup instead of one
+// per wave), and the workgroup barrier after thread 0's agent-scope acquire
+// orders every wave's later loads after it.  Returns false if the wait
+// timed out or another workgroup reported an error.
 __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, unsigned spin_limit) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
   __shared__ int ok;
+  __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned target = k * gridDim.x;
     __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     unsigned spins = 0;
     int good = 1;
     // poll with relaxed loads (an acquire per poll would invalidate the
-    // CU's L1 under the workgroups still computing); acquire once below
+    // caches under the workgroups still computing); acquire once below
     while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > spin_limit) {
         good = 0;
@@ -65,10 +67,10 @@ __device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, unsigned
       __builtin_amdgcn_s_sleep(2);
     }
     if (!good) __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok = good;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return ok != 0;
 }
 
