@@ -19,6 +19,7 @@ namespace {
 
 constexpr int kMaxChunks = 8192;          // upper bound of persistent workgroups
 constexpr unsigned kSpinLimit = 1u << 25; // bounded barrier wait (~1-2 s)
+constexpr int kMaxWgPerCu = 3;            // persistent workgroups per CU
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -163,6 +164,10 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   if (e == hipSuccess) e = nlse_batch_occupancy(dtype, (flags & NLSE_COMPENSATED) ? 1 : 0, &occ);
   if (e != hipSuccess) return nlse_hip_fail(e, "querying occupancy");
   if (occ < 1 || cus < 1) return nlse_fail(NLSE_EDEVICE, "the batched kernel does not fit on a CU");
+  // Each grid barrier costs one L2 write-back and invalidate per workgroup,
+  // serialised per XCD, while the item pipeline already keeps the memory
+  // system busy with three workgroups per CU: cap there.
+  occ = std::min(occ, kMaxWgPerCu);
   int64_t nchunks = std::min<int64_t>({(int64_t)occ * cus, items, (int64_t)kMaxChunks});
 
   nlse_batch* B = new (std::nothrow) nlse_batch();
