@@ -82,6 +82,14 @@ static int check_shape(int ndim, const int64_t dims[3], Shape* s) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Non-temporal own-point accesses pay off once a stage's fields (four
+// field-sized arrays) no longer fit the 256 MB last-level cache; on smaller
+// grids the next stage finds its input there.  1D grids never get here.
+static bool use_streaming(const Shape& s, int dtype) {
+  const double field = (double)s.npts * (dtype == NLSE_F32 ? 8.0 : 16.0);
+  return s.ndim >= 2 && 4.0 * field > 256.0 * (1 << 20);
+}
+
 struct Layout {
   size_t acc, bufA, bufB, lo, partials, out, zero, total;
 };
@@ -261,6 +269,7 @@ static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt,
   L.V = g->V;
   L.vzero = g->work + g->lay.zero;
   L.comp = (g->flags & NLSE_COMPENSATED) ? 1 : 0;
+  L.stream = use_streaming(g->shape, g->dtype) ? 1 : 0;
   L.a = g->a;
   L.s = g->s;
   L.h = g->h;
@@ -486,6 +495,7 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   L.V = g->V;
   L.vzero = g->work + g->lay.zero;
   L.comp = (g->flags & NLSE_COMPENSATED) ? 1 : 0;
+  L.stream = use_streaming(g->shape, g->dtype) ? 1 : 0;
   L.a = g->a;
   L.s = g->s;
   L.h = g->h;

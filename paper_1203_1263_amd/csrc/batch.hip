@@ -150,23 +150,23 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
   auto words = [&](int it) { return item_words(B.items, min(it, i1 - 1)); };
   auto issue = [&](const ItemArgs<T>& I, Regs& r) {
     if (I.order == 4)
-      tile2d_load<T, STAGE, COMP, TX, TY, 2>(I.A, I.tx, I.ty, r);
+      tile2d_load<T, STAGE, COMP, TX, TY, 2, true>(I.A, I.tx, I.ty, r);
     else
-      tile2d_load<T, STAGE, COMP, TX, TY, 1>(I.A, I.tx, I.ty, r);
+      tile2d_load<T, STAGE, COMP, TX, TY, 1, true>(I.A, I.tx, I.ty, r);
   };
   auto compute = [&](const ItemArgs<T>& I, const Regs& r, int buf) {
     cpx<T>* sU = S.u[buf];
     T* sV = S.v[buf];
     if (I.order == 4) {
       if (I.bc == kMSD)
-        tile2d_compute<T, 4, kMSD, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+        tile2d_compute<T, 4, kMSD, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
       else
-        tile2d_compute<T, 4, kDirichlet, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+        tile2d_compute<T, 4, kDirichlet, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
     } else {
       if (I.bc == kMSD)
-        tile2d_compute<T, 2, kMSD, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+        tile2d_compute<T, 2, kMSD, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
       else
-        tile2d_compute<T, 2, kDirichlet, STAGE, COMP, TX, TY>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+        tile2d_compute<T, 2, kDirichlet, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
     }
   };
   // Item `it`: its loads are in flight in `cur`, its descriptor words (long

@@ -130,33 +130,60 @@ struct Own {
   cpx<T> psi, acc, lo;
 };
 
-template <typename T, int STAGE, int COMP>
+// Own-point operands are read once and stage results written once per
+// launch.  When a grid's fields are much larger than the last-level cache
+// (STREAM = true) these accesses are non-temporal, which leaves the caches to
+// the stencil's halo data; on grids that fit, ordinary accesses let the
+// next stage find its input in the cache.
+template <typename T, bool STREAM>
+__device__ __forceinline__ cpx<T> ld_own(const cpx<T>* p) {
+  if constexpr (STREAM) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+    return mk<T>(v.x, v.y);
+  } else {
+    return *p;
+  }
+}
+
+template <typename T, bool STREAM>
+__device__ __forceinline__ void st_own(cpx<T>* p, cpx<T> c) {
+  if constexpr (STREAM) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = {c.re, c.im};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2*>(p));
+  } else {
+    *p = c;
+  }
+}
+
+template <typename T, int STAGE, int COMP, bool STREAM = false>
 __device__ __forceinline__ void load_own(const StageArgs<T>& A, int64_t i, Own<T>& o) {
   if constexpr (STAGE == 2 || STAGE == 3) {
-    o.psi = A.psi[i];
-    o.acc = A.acc[i];
+    o.psi = ld_own<T, STREAM>(A.psi + i);
+    o.acc = ld_own<T, STREAM>(A.acc + i);
   } else if constexpr (STAGE == 4) {
-    o.acc = A.acc[i];
+    o.acc = ld_own<T, STREAM>(A.acc + i);
     if constexpr (COMP) {
-      o.psi = A.uout[i];
-      o.lo = A.lo[i];
+      o.psi = ld_own<T, STREAM>(A.uout + i);
+      o.lo = ld_own<T, STREAM>(A.lo + i);
     }
   }
 }
 
-template <typename T, int STAGE, int COMP>
+template <typename T, int STAGE, int COMP, bool STREAM = false>
 __device__ __forceinline__ void stage_update(const StageArgs<T>& A, int64_t i, cpx<T> u, cpx<T> K,
                                              const Own<T>& o) {
   const T ca = A.c_acc, cn = A.c_next;
   if constexpr (STAGE == 1) {
     cpx<T> acc = COMP ? mk<T>(ca * K.re, ca * K.im) : mk<T>(fmaT(ca, K.re, u.re), fmaT(ca, K.im, u.im));
-    A.acc[i] = acc;
-    A.uout[i] = mk<T>(fmaT(cn, K.re, u.re), fmaT(cn, K.im, u.im));
+    st_own<T, STREAM>(A.acc + i, acc);
+    st_own<T, STREAM>(A.uout + i, mk<T>(fmaT(cn, K.re, u.re), fmaT(cn, K.im, u.im)));
   } else if constexpr (STAGE == 2 || STAGE == 3) {
-    A.acc[i] = mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im));
-    A.uout[i] = mk<T>(fmaT(cn, K.re, o.psi.re), fmaT(cn, K.im, o.psi.im));
+    st_own<T, STREAM>(A.acc + i, mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im)));
+    st_own<T, STREAM>(A.uout + i, mk<T>(fmaT(cn, K.re, o.psi.re), fmaT(cn, K.im, o.psi.im)));
   } else if constexpr (!COMP) {
-    A.uout[i] = mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im));
+    st_own<T, STREAM>(A.uout + i, mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im)));
   } else {
     // Psi_hi + Psi_lo + (acc + k/6 K4), summed in FP64 and split back.
     double inc_r = __builtin_fma(A.c_acc_d, (double)K.re, (double)o.acc.re);
@@ -164,8 +191,8 @@ __device__ __forceinline__ void stage_update(const StageArgs<T>& A, int64_t i, c
     double sr = ((double)o.psi.re + (double)o.lo.re) + inc_r;
     double si = ((double)o.psi.im + (double)o.lo.im) + inc_i;
     T hr = (T)sr, hi = (T)si;
-    A.uout[i] = mk<T>(hr, hi);
-    A.lo[i] = mk<T>((T)(sr - (double)hr), (T)(si - (double)hi));
+    st_own<T, STREAM>(A.uout + i, mk<T>(hr, hi));
+    st_own<T, STREAM>(A.lo + i, mk<T>((T)(sr - (double)hr), (T)(si - (double)hi)));
   }
 }
 

@@ -22,6 +22,7 @@ struct StageLaunch {
   const void* V;
   const void* vzero;  // device zero of the element type, read when V is null
   int stage, comp;
+  int stream;  // non-temporal own-point accesses (fields far larger than the last-level cache)
   double a, s, h;
   double c_acc, c_next;
   int tile[3];

@@ -24,13 +24,16 @@
 
 // Iterations of loads in flight: 1 (two register sets) or 2 (three sets,
 // one wave less occupancy at 32x8; measured slower at 256^3).
+#ifndef NLSE_3D_EXTRA_LDS
+#define NLSE_3D_EXTRA_LDS 0
+#endif
 #ifndef NLSE_3D_DEPTH
 #define NLSE_3D_DEPTH 1
 #endif
 
 namespace nlse {
 
-template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY>
+template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY, bool STREAM>
 __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz) {
   constexpr int NT = TX * TY;
   constexpr int H = ORDER == 4 ? 2 : 1;
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   auto load_pipe = [&](int zplane, int zown, Pipe& p) {
     load_regs(zplane, p.r);
     const StageArgs<T> Po = plane_args(zown);
-    load_own<T, STAGE, COMP>(Po, c32, p.own);
+    load_own<T, STAGE, COMP, STREAM>(Po, c32, p.own);
     p.vq = vload(Po, q32);
   };
   // CD2 at stage-input position i of plane zp (z-neighbours from LDS too).
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     const cpx<T> Kq = rhs(ph, L, uq, nlin(ph, uq, cur.vq));
     cpx<T> K = Kq;
     if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
-    if (store) stage_update<T, STAGE, COMP>(plane_args(z), c32, u0, K, cur.own);
+    if (store) stage_update<T, STAGE, COMP, STREAM>(plane_args(z), c32, u0, K, cur.own);
     // boundary planes: F_b from the interior neighbour in plane 1 / nz-2
     if (z == 1 || z == nz - 2) {
       for (int zz = 0; zz < 2; ++zz) {
@@ -284,10 +287,10 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
         if ((zz == 0 && z != 1) || (zz == 1 && z != nz - 2)) continue;
         const StageArgs<T> Pb = plane_args(zbp);
         Own<T> o;
-        load_own<T, STAGE, COMP>(Pb, c32, o);
+        load_own<T, STAGE, COMP, STREAM>(Pb, c32, o);
         const cpx<T> ub = slot(zbp)[oi];
         const cpx<T> Kb = (BC == kMSD) ? msd_rhs(Kq, uq, ub) : czero<T>();
-        if (store) stage_update<T, STAGE, COMP>(Pb, c32, ub, Kb, o);
+        if (store) stage_update<T, STAGE, COMP, STREAM>(Pb, c32, ub, Kb, o);
       }
     }
     if constexpr (ORDER == 4) dm = dslot(z)[di];
@@ -319,10 +322,15 @@ struct Launch3D {
     const int tx = L.tile[0], ty = L.tile[1], cz = L.tile[2];
     if (cz < 1) return hipErrorInvalidValue;
     const int nb = cdiv(L.n[0], tx) * cdiv(L.n[1], ty) * cdiv(L.n[2] - 2, cz);
-#define NLSE_L3(TX_, TY_)                                                                                  \
-  if (tx == TX_ && ty == TY_) {                                                                            \
-    hipLaunchKernelGGL((stage3d_kernel<T, O, B, S, C, TX_, TY_>), dim3(nb), dim3(TX_ * TY_), 0, st, A, cz); \
-    return hipGetLastError();                                                                              \
+#define NLSE_L3(TX_, TY_)                                                                          \
+  if (tx == TX_ && ty == TY_) {                                                                    \
+    if (L.stream)                                                                                  \
+      hipLaunchKernelGGL((stage3d_kernel<T, O, B, S, C, TX_, TY_, true>), dim3(nb), dim3(TX_ * TY_), \
+                         NLSE_3D_EXTRA_LDS, st, A, cz);                                            \
+    else                                                                                           \
+      hipLaunchKernelGGL((stage3d_kernel<T, O, B, S, C, TX_, TY_, false>), dim3(nb), dim3(TX_ * TY_), \
+                         NLSE_3D_EXTRA_LDS, st, A, cz);                                            \
+    return hipGetLastError();                                                                      \
   }
     NLSE_L3(32, 8)
     NLSE_L3(64, 4)

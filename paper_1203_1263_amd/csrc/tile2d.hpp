@@ -44,7 +44,7 @@ __device__ __forceinline__ int box_elem(int k) {
 }
 
 // Issue all global loads of tile (tx, ty) with halo H into R.
-template <typename T, int STAGE, int COMP, int TX, int TY, int H>
+template <typename T, int STAGE, int COMP, int TX, int TY, int H, bool STREAM = false>
 __device__ __forceinline__ void tile2d_load(const StageArgs<T>& A, int tx, int ty, TileRegs<T, TX, TY>& R) {
   constexpr int BW = TX + 2 * H;
   const int nx = A.nx, ny = A.ny;
@@ -64,7 +64,7 @@ __device__ __forceinline__ void tile2d_load(const StageArgs<T>& A, int tx, int t
   for (int k = 0; k < PF; ++k) R.u[k] = A.uin[off[k]];
 #pragma unroll
   for (int k = 0; k < PF; ++k) R.v[k] = vload(A, off[k]);
-  load_own<T, STAGE, COMP>(A, (int64_t)y * nx + x, R.own);
+  load_own<T, STAGE, COMP, STREAM>(A, (int64_t)y * nx + x, R.own);
 }
 
 // Stage tile (tx, ty) from the loads in R.  sU, sV hold the (TY+2H)(TX+2H)
@@ -73,7 +73,7 @@ __device__ __forceinline__ void tile2d_load(const StageArgs<T>& A, int tx, int t
 // after this workgroup's earlier reads of sU and sV only through the caller
 // (a single-tile kernel has none; the batched kernel alternates two sU / sV
 // buffers), while sD is rewritten only after that barrier.
-template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY>
+template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY, bool STREAM = false>
 __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, int ty, const TileRegs<T, TX, TY>& R,
                                                cpx<T>* __restrict__ sU, T* __restrict__ sV,
                                                cpx<T>* __restrict__ sD) {
@@ -168,7 +168,7 @@ __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, in
   }
   cpx<T> K = Kq;
   if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
-  if (store) stage_update<T, STAGE, COMP>(A, idx, u0, K, R.own);
+  if (store) stage_update<T, STAGE, COMP, STREAM>(A, idx, u0, K, R.own);
 }
 
 // LDS of one tile: box of the stage input and of the potential, D ring.
@@ -183,12 +183,12 @@ struct TileLds {
 
 // One TX x TY tile (tile indices tx, ty) of one RK4 stage, loads then
 // arithmetic.  Contains barriers: every thread of the workgroup must call it.
-template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY>
+template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY, bool STREAM>
 __device__ __forceinline__ void tile2d(const StageArgs<T>& A, int tx, int ty,
                                        TileLds<T, TX, TY, ORDER == 4 ? 2 : 1>& S) {
   TileRegs<T, TX, TY> R;
-  tile2d_load<T, STAGE, COMP, TX, TY, ORDER == 4 ? 2 : 1>(A, tx, ty, R);
-  tile2d_compute<T, ORDER, BC, STAGE, COMP, TX, TY>(A, tx, ty, R, S.u, S.v, S.d);
+  tile2d_load<T, STAGE, COMP, TX, TY, ORDER == 4 ? 2 : 1, STREAM>(A, tx, ty, R);
+  tile2d_compute<T, ORDER, BC, STAGE, COMP, TX, TY, STREAM>(A, tx, ty, R, S.u, S.v, S.d);
 }
 
 }  // namespace nlse
