@@ -64,6 +64,13 @@ enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1 };    /* boundary condition      *
                                  combination of the last stage done in FP64 */
 #define NLSE_NO_GRAPH 0x2u    /* batch only: launch directly instead of
                                  replaying a captured HIP graph */
+#define NLSE_FUSED_PAIRS 0x4u /* grid only, 3D FP32 2SHOC on the 32x8 tile:
+                                 run each pair of RK4 steps as four fused
+                                 launches (stages 1+2, 3+4 per step) that
+                                 keep U1 and U3 on chip (80 instead of 168 B
+                                 per point-step, same bits).  Off by
+                                 default: at 2 workgroups per CU it is
+                                 currently slower than four passes. */
 
 typedef struct nlse_grid nlse_grid;
 
@@ -96,7 +103,7 @@ int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype,
  *   work_dev  device buffer of >= nlse_workspace_bytes() bytes, 256-byte
  *             aligned (borrowed; its contents are owned by the grid).
  *   h, a, s   spacing, dispersion a > 0, nonlinearity s (finite).
- *   flags     0 or NLSE_COMPENSATED (FP32 only).
+ *   flags     0, NLSE_COMPENSATED (FP32 only), NLSE_FUSED_PAIRS.
  * The compensation term starts at zero.  Enqueues its initialisation on the
  * stream.  On success *g receives the new grid. */
 int nlse_create_grid(nlse_grid **g, int ndim, const int64_t dims[3], double h,
@@ -111,7 +118,9 @@ int nlse_set_potential(nlse_grid *g, const void *V_dev);
 /* Advance nsteps classic RK4 steps of size dt (Eq. RK4) with Laplacian
  * `order` (NLSE_CD2 or NLSE_2SHOC) and boundary condition `bc`.  Each step is
  * four fused stage kernels (stencil, boundary update and RK4 accumulation in
- * one pass each).  Psi is updated in place; asynchronous.  dt > 0 finite,
+ * one pass each); grids created with NLSE_FUSED_PAIRS run two launches per
+ * step instead (stages 1+2 and 3+4), with the same bits.
+ * Psi is updated in place; asynchronous.  dt > 0 finite,
  * nsteps >= 0.  A dt above nlse_dt_max() is allowed (blow-up shows up as
  * NLSE_EUNSTABLE from nlse_mass_energy). */
 int nlse_step_rk4(nlse_grid *g, int order, int bc, double dt, int64_t nsteps);
@@ -138,7 +147,8 @@ int nlse_set_state(nlse_grid *g, const void *lo_dev);
  * z-chunk length (unused entries 1).  Any supported shape gives bitwise
  * identical results.  nlse_autotune times the candidates for
  * (order, bc) on this grid (running stage kernels on scratch copies, the
- * field is not changed), keeps the fastest and stores it in the cache file
+ * field is not changed; for fused 3D grids only the z-chunk of the 32x8
+ * tile is tuned), keeps the fastest and stores it in the cache file
  * named by $NLSE_TUNE_CACHE if set.  nlse_set_tile forces a shape
  * (NLSE_EUNSUPPORTED if it is not a compiled candidate). */
 int nlse_autotune(nlse_grid *g, int order, int bc, double dt);

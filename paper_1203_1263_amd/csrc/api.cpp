@@ -158,7 +158,7 @@ extern "C" int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype, 
   int rc = check_shape(ndim, dims, &s);
   if (rc) return rc;
   if (dtype != NLSE_F32 && dtype != NLSE_F64) return fail(NLSE_EINVAL, "dtype must be NLSE_F32 or NLSE_F64");
-  if (flags & ~NLSE_COMPENSATED) return fail(NLSE_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(NLSE_COMPENSATED | NLSE_FUSED_PAIRS)) return fail(NLSE_EINVAL, "unknown flag bits 0x%x", flags);
   if ((flags & NLSE_COMPENSATED) && dtype != NLSE_F32)
     return fail(NLSE_EUNSUPPORTED, "NLSE_COMPENSATED applies to FP32 grids only");
   if (!bytes) return fail(NLSE_EINVAL, "bytes is NULL");
@@ -167,8 +167,13 @@ extern "C" int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype, 
 }
 
 // Default tile shapes (x-width, y-height, z-chunk) per dimension.
-static void default_tile(const Shape& s, int dtype, int order, int t[3]) {
-  (void)order;
+// A 3D FP32 2SHOC grid created with NLSE_FUSED_PAIRS runs each step as two
+// fused launches (S1+S2, S3+S4) when its order-4 tile is 32x8.
+static bool fused_eligible(const Shape& s, int dtype, unsigned flags, int order) {
+  return s.ndim == 3 && dtype == NLSE_F32 && order == 4 && (flags & NLSE_FUSED_PAIRS);
+}
+
+static void default_tile(const Shape& s, int dtype, unsigned flags, int order, int t[3]) {
   if (s.ndim == 1) {
     t[0] = 256; t[1] = 1; t[2] = 1;
   } else if (s.ndim == 2) {
@@ -183,9 +188,10 @@ static void default_tile(const Shape& s, int dtype, int order, int t[3]) {
     if (nch < 1) nch = 1;
     int64_t cz = (nzi + nch - 1) / nch;
     if (cz < 8) cz = 8;
+    // the fused kernels fill a 7-plane pipeline per chunk: longer chunks
+    if (fused_eligible(s, dtype, flags, order)) cz = 32;
     if (cz > nzi) cz = nzi;
     t[2] = (int)cz;
-    (void)dtype;
   }
 }
 
@@ -223,8 +229,8 @@ extern "C" int nlse_create_grid(nlse_grid** g, int ndim, const int64_t dims[3], 
   G->lay = layout_for(G->shape, dtype, flags);
   G->stream = static_cast<hipStream_t>(hip_stream);
   G->V = nullptr;
-  default_tile(G->shape, dtype, 2, G->tile[0]);
-  default_tile(G->shape, dtype, 4, G->tile[1]);
+  default_tile(G->shape, dtype, flags, 2, G->tile[0]);
+  default_tile(G->shape, dtype, flags, 4, G->tile[1]);
   hipError_t e = nlse_launch_fill_zero(G->work + G->lay.zero, 256, G->stream);
   if (e == hipSuccess && (flags & NLSE_COMPENSATED))
     e = nlse_launch_fill_zero(G->work + G->lay.lo, (int64_t)G->shape.npts * 8, G->stream);
@@ -258,8 +264,8 @@ static int check_scheme(int order, int bc) {
 }
 
 // Enqueue one RK4 step (four stage launches) with the given tile.
-static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt, const int tile[3],
-                               hipStream_t st) {
+// The grid-wide part of a stage launch.
+static nlse::StageLaunch grid_launch(const nlse_grid* g, int order, int bc, const int tile[3]) {
   nlse::StageLaunch L;
   L.ndim = g->shape.ndim;
   L.dtype = g->dtype;
@@ -274,6 +280,12 @@ static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt,
   L.s = g->s;
   L.h = g->h;
   for (int d = 0; d < 3; ++d) L.tile[d] = tile[d];
+  return L;
+}
+
+static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt, const int tile[3],
+                               hipStream_t st) {
+  nlse::StageLaunch L = grid_launch(g, order, bc, tile);
   void* psi = g->psi;
   void* acc = g->work + g->lay.acc;
   void* A = g->work + g->lay.bufA;
@@ -306,7 +318,23 @@ extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t
   if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
   if (nsteps < 0) return fail(NLSE_EINVAL, "nsteps must be >= 0");
   const int* tile = g->tile[tile_slot(order)];
-  for (int64_t n = 0; n < nsteps; ++n) {
+  int64_t left = nsteps;
+  if (fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 && tile[1] == 8) {
+    // Pairs of steps Psi -> workspace -> Psi (the fused launches cannot
+    // update Psi in place); an odd last step takes the four-pass kernels,
+    // which give the same bits.
+    nlse::StageLaunch L = grid_launch(g, order, bc, tile);
+    void* acc = g->work + g->lay.acc;
+    void* mid = g->work + g->lay.bufA;
+    void* alt = g->work + g->lay.bufB;
+    void* lo = L.comp ? g->work + g->lay.lo : nullptr;
+    for (; left >= 2; left -= 2) {
+      hipError_t e = nlse_launch_fused3d(L, g->psi, alt, acc, mid, lo, dt, g->stream);
+      if (e == hipSuccess) e = nlse_launch_fused3d(L, alt, g->psi, acc, mid, lo, dt, g->stream);
+      if (e != hipSuccess) return hip_fail(e, "fused stage launch");
+    }
+  }
+  for (; left > 0; --left) {
     hipError_t e = enqueue_step(g, order, bc, dt, tile, g->stream);
     if (e != hipSuccess) return hip_fail(e, "stage launch");
   }
@@ -413,6 +441,14 @@ static std::vector<std::array<int, 3>> candidates(const nlse_grid* g, int order)
     out.push_back({256, 1, 1});
   } else if (s.ndim == 2) {
     for (auto t : {std::array<int, 3>{32, 8, 1}, {64, 4, 1}, {64, 8, 1}}) out.push_back(t);
+  } else if (fused_eligible(s, g->dtype, g->flags, order)) {
+    const int64_t nzi = s.n[2] - 2;
+    for (int cz : {16, 32, 64, 128}) {
+      std::array<int, 3> t = {32, 8, (int)std::min<int64_t>(cz, nzi)};
+      bool dup = false;
+      for (auto& o : out) dup |= (o == t);
+      if (!dup) out.push_back(t);
+    }
   } else {
     const int64_t nzi = s.n[2] - 2;
     for (auto xy : {std::array<int, 2>{32, 8}, {64, 4}, {64, 8}})
@@ -463,8 +499,9 @@ static void cache_store(const std::string& key, const int t[3], float ms) {
   fclose(f);
 }
 
-// Times stages 1-3 only (they read Psi but never write it), so the field is
-// left untouched; the accumulator and stage buffers are scratch.
+// Times stages 1-3 only (they read Psi but never write it), or the first
+// fused pair (stages 1+2), so the field is left untouched; the accumulator
+// and stage buffers are scratch.
 extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
   int rc = check_scheme(order, bc);
@@ -507,9 +544,17 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   float best = 1e30f;
   std::array<int, 3> best_t = cands[0];
   const int reps = g->shape.npts > (1 << 20) ? 5 : 20;
+  const bool fused = fused_eligible(g->shape, g->dtype, g->flags, order);
   for (auto& t : cands) {
     for (int d = 0; d < 3; ++d) L.tile[d] = t[d];
     auto run = [&](int n) -> hipError_t {
+      if (fused) {
+        for (int r = 0; r < n; ++r) {
+          hipError_t ee = nlse_launch_fused3d_pair0(L, g->psi, L.acc, A, dt, g->stream);
+          if (ee != hipSuccess) return ee;
+        }
+        return hipSuccess;
+      }
       for (int r = 0; r < n; ++r)
         for (int k = 1; k <= 3; ++k) {
           L.stage = k;

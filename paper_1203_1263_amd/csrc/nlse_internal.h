@@ -46,6 +46,14 @@ inline int64_t reduce_blocks(int64_t npts) { return (npts + kReduceChunk - 1) / 
 }  // namespace nlse
 
 hipError_t nlse_launch_stage(const nlse::StageLaunch& L, hipStream_t st);
+// One RK4 step of a 3D FP32 2SHOC grid as two fused launches (stages 1+2
+// into acc and mid = U2, stages 3+4 into psi_out and lo); psi_out must not
+// be psi_in.  L.tile[2] = z-chunk.
+hipError_t nlse_launch_fused3d(const nlse::StageLaunch& L, const void* psi_in, void* psi_out, void* acc, void* mid,
+                               void* lo, double dt, hipStream_t st);
+// Only the first fused launch (reads psi, writes acc and mid): for timing.
+hipError_t nlse_launch_fused3d_pair0(const nlse::StageLaunch& L, const void* psi, void* acc, void* mid, double dt,
+                                     hipStream_t st);
 hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st);
 hipError_t nlse_launch_fill_zero(void* p, int64_t nbytes, hipStream_t st);
 extern "C" int nlse_internal_tile_supported(int ndim, int dtype, const int tile[3]);

@@ -98,6 +98,30 @@ def test_tile_shape_bit_invariance(nd, order, bc):
         assert np.array_equal(o, outs[0])
 
 
+FUSED_CASES = [((19, 21, 133), "msd", True, True, 16), ((19, 21, 133), "dirichlet", False, True, 5),
+               ((3, 3, 3), "msd", True, True, 1), ((4, 9, 40), "msd", False, False, 1),
+               ((5, 10, 33), "dirichlet", True, True, 2), ((12, 17, 31), "msd", True, False, 3),
+               ((40, 12, 70), "msd", True, True, 7), ((40, 12, 70), "msd", False, True, 38)]
+
+
+@pytest.mark.parametrize("shape,bc,comp,withV,cz", FUSED_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-{c[1]}-c{int(c[2])}-v{int(c[3])}-cz{c[4]}"
+                              for c in FUSED_CASES])
+def test_fused_pairs_equal_four_passes(shape, bc, comp, withV, cz):
+    """3D FP32 2SHOC with NLSE_FUSED_PAIRS: the two fused launches per step
+    (stages 1+2, 3+4; an odd last step takes four passes) give the bits of
+    the four single-stage launches, for ragged shapes, tiny nz, every z-chunk
+    length and both boundary conditions."""
+    u, V, h, a, s = smooth_problem(shape, 60 + cz, V=withV)
+    dt = 0.5 * oracle.dt_max(3, 4, h, a)
+    fused = run_gpu(u, h, a, s, dt, 7, V=V, order=4, bc=bc, dtype="f32", compensated=comp, tile=(32, 8, cz),
+                    fused_pairs=True)
+    four = run_gpu(u, h, a, s, dt, 7, V=V, order=4, bc=bc, dtype="f32", compensated=comp, tile=(32, 8, cz))
+    assert np.array_equal(fused, four)
+    ref = oracle.rk4(u, h, a, s, dt, 7, V=V, order=4, bc=bc)
+    assert rel_l2(fused, ref) < TOL["f32"]
+
+
 def test_run_twice_bitwise():
     u, V, h, a, s = smooth_problem((17, 23, 91), 3)
     dt = 0.5 * oracle.dt_max(3, 4, h, a)
