@@ -7,15 +7,17 @@
 // Activations are NHWC BF16 with the channel count padded to a multiple of 8
 // (input 2 -> 8, last-layer output 2 -> 16).  A 3x3 convolution is an implicit
 // GEMM: D[co][pixel] = sum_k W[co][k] X[k][pixel] with k = (tap, ci), tap =
-// 3 ky + kx.  A workgroup computes a 16x16 pixel tile for every output
-// channel: the weights ([co][tap][ci], K contiguous) and the input tile with a
-// one-pixel halo ([pixel][ci]) sit in LDS; each wave owns four pixel rows and
-// all channel blocks.  The backward data pass is the same kernel with flipped
+// 3 ky + kx.  A persistent workgroup computes 16x16 pixel tiles for every
+// output channel: the weights ([co][tap][ci], K contiguous, staged once) and
+// the input tile with a one-pixel halo ([pixel][ci]) sit in LDS; each wave
+// owns four pixel rows and all channel blocks.  The backward data pass is the same kernel with flipped
 // taps and transposed channels, masked by the ReLU of the stored activation.
 // The weight gradient is a second MFMA kernel (pixels are the reduction
 // dimension) writing per-workgroup partials that a fixed-order pass sums, so
 // gradients are bitwise reproducible.
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "nlse_device.hpp"
 #include "nlse_surrogate.h"
@@ -59,103 +61,142 @@ struct ConvArgs {
 
 enum { kEpiRelu = 0, kEpiLast = 1, kEpiDgrad = 2 };
 
+// Persistent: a workgroup stages the layer's weights in LDS once and then
+// walks pixel tiles tile = blockIdx.x, + gridDim.x, ...; the input of its
+// next tile is loaded into registers while the current tile is computed.
+// LDS rows are padded by 16 bytes (weights: K + 8, pixels: CIN + 8 BF16
+// values) so the 16-byte operand reads of 16 lanes hit distinct banks.
 template <int CIN, int COUT, int EPI>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a) {
+__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntiles) {
   constexpr int K = 9 * CIN;
+  constexpr int KP = K + 8;    // padded weight row
+  constexpr int CP = CIN + 8;  // padded input pixel
   constexpr int KSTEPS = (K + 31) / 32;
   constexpr int NCB = COUT / 16;
   constexpr int CH = CIN / 8;  // 16-byte chunks per input pixel
-  __shared__ __attribute__((aligned(16))) uint16_t sIn[18 * 18 * CIN];
-  __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * K];
+  constexpr int NCHUNK = 18 * 18 * CH;
+  constexpr int NLD = (NCHUNK + 255) / 256;
+  __shared__ __attribute__((aligned(16))) uint16_t sIn[18 * 18 * CP];
+  __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * KP];
 
   const int tid = threadIdx.x;
   const int tilesx = a.W / 16, tilesy = a.H / 16;
-  const int t = blockIdx.x;
-  const int b = t / (tilesx * tilesy);
-  const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
-  const int x0 = tx * 16, y0 = ty * 16;
-  const int64_t img = (int64_t)b * a.H * a.W;
 
-  // weights -> LDS (16-byte chunks; COUT*K*2 is a multiple of 16)
+  // weights -> LDS once (16-byte chunks; K is a multiple of 8)
   {
     const uint4* src = reinterpret_cast<const uint4*>(a.w);
     uint4* dst = reinterpret_cast<uint4*>(sW);
-    for (int i = tid; i < COUT * K / 8; i += 256) dst[i] = src[i];
-  }
-  // input tile with a one-pixel halo -> LDS, zero outside the image
-  {
-    uint4* dst = reinterpret_cast<uint4*>(sIn);
-    for (int i = tid; i < 18 * 18 * CH; i += 256) {
-      const int pp = i / CH, part = i - pp * CH;
-      const int py = pp / 18, px = pp - py * 18;
-      const int gy = y0 - 1 + py, gx = x0 - 1 + px;
-      uint4 v = zero4();
-      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-        v = reinterpret_cast<const uint4*>(a.in + (img + (int64_t)gy * a.W + gx) * CIN)[part];
-      dst[i] = v;
+    for (int i = tid; i < COUT * K / 8; i += 256) {
+      const int row = i / (K / 8), c = i - row * (K / 8);
+      dst[row * (KP / 8) + c] = src[i];
     }
   }
-  __syncthreads();
+
+  // input tile with a one-pixel halo, zero outside the image
+  uint4 pre[NLD];
+  auto load_tile = [&](int t) {
+    const int b = t / (tilesx * tilesy);
+    const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
+    const int64_t img = (int64_t)b * a.H * a.W;
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = tid + 256 * k;
+      uint4 v = zero4();
+      if (i < NCHUNK) {
+        const int pp = i / CH, part = i - pp * CH;
+        const int py = pp / 18, px = pp - py * 18;
+        const int gy = ty * 16 - 1 + py, gx = tx * 16 - 1 + px;
+        if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+          v = reinterpret_cast<const uint4*>(a.in + (img + (int64_t)gy * a.W + gx) * CIN)[part];
+      }
+      pre[k] = v;
+    }
+  };
+  auto store_tile = [&]() {
+    uint4* dst = reinterpret_cast<uint4*>(sIn);
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = tid + 256 * k;
+      if (i < NCHUNK) {
+        const int pp = i / CH, part = i - pp * CH;
+        dst[pp * (CP / 8) + part] = pre[k];
+      }
+    }
+  };
 
   const int wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, g = lane >> 4;
-  f32x4 acc[NCB][4];
-#pragma unroll
-  for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+  int t = blockIdx.x;
+  if (t < ntiles) load_tile(t);
+  for (; t < ntiles; t += gridDim.x) {
+    __syncthreads();  // the previous tile's operand reads are done (and the weights are in)
+    store_tile();
+    __syncthreads();
+    if (t + (int)gridDim.x < ntiles) load_tile(t + gridDim.x);
 
-#pragma unroll 2
-  for (int ks = 0; ks < KSTEPS; ++ks) {
-    const int k0 = 32 * ks + 8 * g;
-    const bool kv = k0 < K;
-    const int tap = kv ? k0 / CIN : 0, ci0 = kv ? k0 % CIN : 0;
-    const int dy = tap / 3, dx = tap - 3 * dy;
-    bf16x8 af[NCB], bfr[4];
+    const int b = t / (tilesx * tilesy);
+    const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
+    const int x0 = tx * 16, y0 = ty * 16;
+    const int64_t img = (int64_t)b * a.H * a.W;
+
+    f32x4 acc[NCB][4];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
-      af[cb] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * K + k0]) : zero4());
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+#pragma unroll 2
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int k0 = 32 * ks + 8 * g;
+      const bool kv = k0 < K;
+      const int tap = kv ? k0 / CIN : 0, ci0 = kv ? k0 % CIN : 0;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      bf16x8 af[NCB], bfr[4];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        af[cb] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * KP + k0]) : zero4());
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr) {
+        const int row = 4 * wave + rr;
+        bfr[rr] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sIn[((row + dy) * 18 + j + dx) * CP + ci0]) : zero4());
+      }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+          acc[cb][rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cb], bfr[rr], acc[cb][rr], 0, 0, 0);
+    }
+
+    // lane holds D[co = 16 cb + 4 g + r][pixel (row, j)], r = 0..3
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
       const int row = 4 * wave + rr;
-      bfr[rr] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sIn[((row + dy) * 18 + j + dx) * CIN + ci0]) : zero4());
-    }
+      const int64_t pix = img + (int64_t)(y0 + row) * a.W + (x0 + j);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int co = 16 * cb + 4 * g;
+        float v[4] = {acc[cb][rr][0], acc[cb][rr][1], acc[cb][rr][2], acc[cb][rr][3]};
+        if constexpr (EPI == kEpiRelu) {
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr)
-        acc[cb][rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cb], bfr[rr], acc[cb][rr], 0, 0, 0);
-  }
-
-  // lane holds D[co = 16 cb + 4 g + r][pixel (row, j)], r = 0..3
+          for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + a.bias[co + r], 0.f);
+        } else if constexpr (EPI == kEpiDgrad) {
+          const uint2 m = *reinterpret_cast<const uint2*>(a.mask + pix * COUT + co);
+          const uint16_t mb[4] = {(uint16_t)(m.x & 0xffffu), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffffu),
+                                  (uint16_t)(m.y >> 16)};
 #pragma unroll
-  for (int rr = 0; rr < 4; ++rr) {
-    const int row = 4 * wave + rr;
-    const int64_t pix = img + (int64_t)(y0 + row) * a.W + (x0 + j);
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      const int co = 16 * cb + 4 * g;
-      float v[4] = {acc[cb][rr][0], acc[cb][rr][1], acc[cb][rr][2], acc[cb][rr][3]};
-      if constexpr (EPI == kEpiRelu) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + a.bias[co + r], 0.f);
-      } else if constexpr (EPI == kEpiDgrad) {
-        const uint2 m = *reinterpret_cast<const uint2*>(a.mask + pix * COUT + co);
-        const uint16_t mb[4] = {(uint16_t)(m.x & 0xffffu), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffffu),
-                                (uint16_t)(m.y >> 16)};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) v[r] = bf16_val(mb[r]) > 0.f ? v[r] : 0.f;
-      }
-      if constexpr (EPI == kEpiLast) {
-        if (g == 0) {  // channels 0, 1 are the real and imaginary increments
-          const float2 xv = a.x[pix];
-          a.pred[pix] = make_float2(xv.x + (v[0] + a.bias[0]), xv.y + (v[1] + a.bias[1]));
+          for (int r = 0; r < 4; ++r) v[r] = bf16_val(mb[r]) > 0.f ? v[r] : 0.f;
         }
-      } else {
-        uint2 o;
-        o.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
-        o.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
-        *reinterpret_cast<uint2*>(a.out + pix * COUT + co) = o;
+        if constexpr (EPI == kEpiLast) {
+          if (g == 0) {  // channels 0, 1 are the real and imaginary increments
+            const float2 xv = a.x[pix];
+            a.pred[pix] = make_float2(xv.x + (v[0] + a.bias[0]), xv.y + (v[1] + a.bias[1]));
+          }
+        } else {
+          uint2 o;
+          o.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
+          o.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+          *reinterpret_cast<uint2*>(a.out + pix * COUT + co) = o;
+        }
       }
     }
   }
@@ -438,6 +479,37 @@ static int grid_for(int64_t n) {
 
 using namespace nlse;
 
+// Compute units of the current device (queried once per process).
+static int cu_count() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                 hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Persistent grid: as many workgroups as the device holds at once (queried
+// once per kernel), never more than there are tiles.
+template <int CIN, int COUT, int EPI>
+static hipError_t launch_conv(const ConvArgs& a, int ntiles, hipStream_t st) {
+  static int per_cu = 0;
+  if (per_cu == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&conv3x3_kernel<CIN, COUT, EPI>),
+                                                     256, 0) != hipSuccess || n < 1)
+      n = 1;
+    per_cu = n;
+  }
+  const dim3 grid((unsigned)std::min(ntiles, per_cu * cu_count()));
+  hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, EPI>), grid, dim3(256), 0, st, a, ntiles);
+  return hipGetLastError();
+}
+
 hipError_t sg_pack_input(const void* psi, void* x, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(pack_input_kernel, dim3(grid_for(n)), dim3(256), 0, st, static_cast<const float2*>(psi),
                      static_cast<uint4*>(x), n);
@@ -455,13 +527,13 @@ hipError_t sg_conv(int kind, const SgConv& c, hipStream_t st) {
   a.mask = c.mask;
   a.H = c.H;
   a.W = c.W;
-  const dim3 grid((unsigned)(c.B * (c.H / 16) * (c.W / 16)));
+  const int ntiles = c.B * (c.H / 16) * (c.W / 16);
   switch (kind) {
-    case kSgFirst: hipLaunchKernelGGL((conv3x3_kernel<8, 48, kEpiRelu>), grid, dim3(256), 0, st, a); break;
-    case kSgHidden: hipLaunchKernelGGL((conv3x3_kernel<48, 48, kEpiRelu>), grid, dim3(256), 0, st, a); break;
-    case kSgLast: hipLaunchKernelGGL((conv3x3_kernel<48, 16, kEpiLast>), grid, dim3(256), 0, st, a); break;
-    case kSgDgradLast: hipLaunchKernelGGL((conv3x3_kernel<16, 48, kEpiDgrad>), grid, dim3(256), 0, st, a); break;
-    case kSgDgradHidden: hipLaunchKernelGGL((conv3x3_kernel<48, 48, kEpiDgrad>), grid, dim3(256), 0, st, a); break;
+    case kSgFirst: return launch_conv<8, 48, kEpiRelu>(a, ntiles, st);
+    case kSgHidden: return launch_conv<48, 48, kEpiRelu>(a, ntiles, st);
+    case kSgLast: return launch_conv<48, 16, kEpiLast>(a, ntiles, st);
+    case kSgDgradLast: return launch_conv<16, 48, kEpiDgrad>(a, ntiles, st);
+    case kSgDgradHidden: return launch_conv<48, 48, kEpiDgrad>(a, ntiles, st);
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -38,6 +38,13 @@ BLOCK = 16
 # algorithmic flops of one forward pass per pixel: 2 per multiply-add over
 # the six 3x3 layers with their real channel counts (2-48-48-48-48-48-2)
 FLOP_PER_PIXEL = 2 * 9 * (2 * 48 + 4 * 48 * 48 + 48 * 2)
+# HBM bytes of one forward pass per pixel, each activation read and written
+# once in the kernels' layout: packing (8 B complex64 in, 16 B = 8 BF16
+# channels out), layer 1 (16 in, 96 out), layers 2-5 (96 in, 96 out), layer 6
+# (96 in, plus the 8 B input field read and the 8 B prediction written).
+# At 169 344 flop per 1016 B (167 flop/B) the pass sits below the BF16 ridge
+# (2.5 PFLOP/s / 8 TB/s = 312 flop/B): it is HBM-bound.
+BYTES_PER_PIXEL = (8 + 16) + (16 + 96) + 4 * (96 + 96) + (96 + 8 + 8)
 
 
 class _P:
@@ -200,8 +207,10 @@ def speedup(m, snaps, batch: int):
     t_sg = _time(surrogate_block, 10)
     t_fwd = _time(lambda: m.forward(fields, out), 10)
     fwd_flop = FLOP_PER_PIXEL * batch * N * N
+    fwd_bytes = BYTES_PER_PIXEL * batch * N * N
     return {"batch": batch, "ms_rk4_16_steps": t_rk, "ms_surrogate_block": t_sg, "speedup": t_rk / t_sg,
-            "ms_forward": t_fwd, "forward_tflops": fwd_flop / (t_fwd * 1e-3) / 1e12}
+            "ms_forward": t_fwd, "forward_tflops": fwd_flop / (t_fwd * 1e-3) / 1e12,
+            "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9}
 
 
 def run(ntraj: int = 200, iters: int = 3000, batch: int = 32, lr: float = 1e-3, seed: int = 0):
