@@ -223,7 +223,8 @@ int nlse_batch_destroy(nlse_batch *b);
  * layers 1-5, zero "same" padding, pred = psi + net(psi).  BF16 weights and
  * activations, FP32 accumulation on the matrix cores, FP32 master weights.
  * Not part of the paper's method: it is trained on trajectories of the
- * integrator above, which stays its fallback and judge.
+ * integrator above, which stays its fallback and the reference its error is
+ * measured against.
  *
  * Parameters: one FP32 device array of nlse_surrogate_param_count() values,
  * per layer W (Cout, Cin, 3, 3) row-major then b (Cout), layers in order.
