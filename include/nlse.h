@@ -62,8 +62,8 @@ enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1 };    /* boundary condition      *
 /* Grid / batch flags. */
 #define NLSE_COMPENSATED 0x1u /* FP32 only: keep Psi as hi+lo pair, RK4
                                  combination of the last stage done in FP64 */
-#define NLSE_NO_GRAPH 0x2u    /* batch only: launch directly instead of
-                                 replaying a captured HIP graph */
+#define NLSE_NO_GRAPH 0x2u    /* grid or batch: launch directly instead of
+                                 replaying captured HIP graphs */
 #define NLSE_FUSED_PAIRS 0x4u /* grid only, 3D FP32 2SHOC on the 32x8 tile:
                                  run each pair of RK4 steps as four fused
                                  launches (stages 1+2, 3+4 per step) that
@@ -103,7 +103,8 @@ int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype,
  *   work_dev  device buffer of >= nlse_workspace_bytes() bytes, 256-byte
  *             aligned (borrowed; its contents are owned by the grid).
  *   h, a, s   spacing, dispersion a > 0, nonlinearity s (finite).
- *   flags     0, NLSE_COMPENSATED (FP32 only), NLSE_FUSED_PAIRS.
+ *   flags     0, NLSE_COMPENSATED (FP32 only), NLSE_FUSED_PAIRS,
+ *             NLSE_NO_GRAPH.
  * The compensation term starts at zero.  Enqueues its initialisation on the
  * stream.  On success *g receives the new grid. */
 int nlse_create_grid(nlse_grid **g, int ndim, const int64_t dims[3], double h,
@@ -119,7 +120,10 @@ int nlse_set_potential(nlse_grid *g, const void *V_dev);
  * `order` (NLSE_CD2 or NLSE_2SHOC) and boundary condition `bc`.  Each step is
  * four fused stage kernels (stencil, boundary update and RK4 accumulation in
  * one pass each); grids created with NLSE_FUSED_PAIRS run two launches per
- * step instead (stages 1+2 and 3+4), with the same bits.
+ * step instead (stages 1+2 and 3+4), with the same bits.  Unless the grid
+ * has NLSE_NO_GRAPH, the launches of up to 64 steps are captured once per
+ * (order, bc, dt, tile, step count) into a HIP graph that is replayed
+ * (setting a different potential drops the captured graphs).
  * Psi is updated in place; asynchronous.  dt > 0 finite,
  * nsteps >= 0.  A dt above nlse_dt_max() is allowed (blow-up shows up as
  * NLSE_EUNSTABLE from nlse_mass_energy). */

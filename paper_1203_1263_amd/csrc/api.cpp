@@ -12,8 +12,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "nlse_internal.h"
@@ -119,6 +121,17 @@ static Layout layout_for(const Shape& s, int dtype, unsigned flags) {
 
 // ---------------------------------------------------------------- grid
 
+// Replayable step sequences: one HIP graph per (order, bc, dt, tile, steps).
+struct GraphKey {
+  int order, bc, steps;
+  uint64_t dt_bits;
+  int tile[3];
+  bool operator<(const GraphKey& o) const {
+    return std::tie(order, bc, steps, dt_bits, tile[0], tile[1], tile[2]) <
+           std::tie(o.order, o.bc, o.steps, o.dt_bits, o.tile[0], o.tile[1], o.tile[2]);
+  }
+};
+
 struct nlse_grid {
   Shape shape;
   int dtype;
@@ -131,7 +144,14 @@ struct nlse_grid {
   hipStream_t stream;
   const void* V;
   int tile[2][3];  // [0] CD2, [1] 2SHOC
+  hipStream_t cap = nullptr;  // private stream used only for graph capture
+  std::map<GraphKey, hipGraphExec_t> graphs;
 };
+
+static void drop_graphs(nlse_grid* g) {
+  for (auto& kv : g->graphs) (void)hipGraphExecDestroy(kv.second);
+  g->graphs.clear();
+}
 
 // Read-only view of a grid for the other C-ABI translation units.
 void nlse_grid_view(const nlse_grid* g, int* ndim, int64_t n[3], int* dtype, unsigned* flags, double* h,
@@ -158,7 +178,8 @@ extern "C" int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype, 
   int rc = check_shape(ndim, dims, &s);
   if (rc) return rc;
   if (dtype != NLSE_F32 && dtype != NLSE_F64) return fail(NLSE_EINVAL, "dtype must be NLSE_F32 or NLSE_F64");
-  if (flags & ~(NLSE_COMPENSATED | NLSE_FUSED_PAIRS)) return fail(NLSE_EINVAL, "unknown flag bits 0x%x", flags);
+  if (flags & ~(NLSE_COMPENSATED | NLSE_FUSED_PAIRS | NLSE_NO_GRAPH))
+    return fail(NLSE_EINVAL, "unknown flag bits 0x%x", flags);
   if ((flags & NLSE_COMPENSATED) && dtype != NLSE_F32)
     return fail(NLSE_EUNSUPPORTED, "NLSE_COMPENSATED applies to FP32 grids only");
   if (!bytes) return fail(NLSE_EINVAL, "bytes is NULL");
@@ -244,6 +265,8 @@ extern "C" int nlse_create_grid(nlse_grid** g, int ndim, const int64_t dims[3], 
 
 extern "C" int nlse_destroy_grid(nlse_grid* g) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  drop_graphs(g);
+  if (g->cap) (void)hipStreamDestroy(g->cap);
   delete g;
   return NLSE_OK;
 }
@@ -252,6 +275,7 @@ extern "C" int nlse_set_potential(nlse_grid* g, const void* V_dev) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
   if (V_dev && ((uintptr_t)V_dev) % (g->dtype == NLSE_F32 ? 4 : 8))
     return fail(NLSE_EINVAL, "V_dev is misaligned");
+  if (V_dev != g->V) drop_graphs(g);  // captured launches hold the old pointer
   g->V = V_dev;
   return NLSE_OK;
 }
@@ -311,13 +335,9 @@ static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt,
   return hipSuccess;
 }
 
-extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t nsteps) {
-  if (!g) return fail(NLSE_EINVAL, "g is NULL");
-  int rc = check_scheme(order, bc);
-  if (rc) return rc;
-  if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
-  if (nsteps < 0) return fail(NLSE_EINVAL, "nsteps must be >= 0");
-  const int* tile = g->tile[tile_slot(order)];
+// Enqueue nsteps RK4 steps on stream st (no host synchronisation).
+static hipError_t enqueue_steps(const nlse_grid* g, int order, int bc, double dt, const int tile[3], int64_t nsteps,
+                                hipStream_t st) {
   int64_t left = nsteps;
   if (fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 && tile[1] == 8) {
     // Pairs of steps Psi -> workspace -> Psi (the fused launches cannot
@@ -329,14 +349,79 @@ extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t
     void* alt = g->work + g->lay.bufB;
     void* lo = L.comp ? g->work + g->lay.lo : nullptr;
     for (; left >= 2; left -= 2) {
-      hipError_t e = nlse_launch_fused3d(L, g->psi, alt, acc, mid, lo, dt, g->stream);
-      if (e == hipSuccess) e = nlse_launch_fused3d(L, alt, g->psi, acc, mid, lo, dt, g->stream);
-      if (e != hipSuccess) return hip_fail(e, "fused stage launch");
+      hipError_t e = nlse_launch_fused3d(L, g->psi, alt, acc, mid, lo, dt, st);
+      if (e == hipSuccess) e = nlse_launch_fused3d(L, alt, g->psi, acc, mid, lo, dt, st);
+      if (e != hipSuccess) return e;
     }
   }
   for (; left > 0; --left) {
-    hipError_t e = enqueue_step(g, order, bc, dt, tile, g->stream);
-    if (e != hipSuccess) return hip_fail(e, "stage launch");
+    hipError_t e = enqueue_step(g, order, bc, dt, tile, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+constexpr int kGraphSteps = 64;  // steps per captured graph
+constexpr size_t kMaxGraphs = 32;
+
+// The graph replaying `steps` steps with the grid's current settings,
+// captured on first use.
+static hipError_t step_graph(nlse_grid* g, int order, int bc, double dt, const int tile[3], int steps,
+                             hipGraphExec_t* out) {
+  GraphKey key;
+  key.order = order;
+  key.bc = bc;
+  key.steps = steps;
+  memcpy(&key.dt_bits, &dt, sizeof dt);
+  for (int d = 0; d < 3; ++d) key.tile[d] = tile[d];
+  auto found = g->graphs.find(key);
+  if (found != g->graphs.end()) {
+    *out = found->second;
+    return hipSuccess;
+  }
+  if (g->graphs.size() >= kMaxGraphs) drop_graphs(g);
+  hipError_t e = hipSuccess;
+  if (!g->cap) e = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return e;
+  hipGraph_t graph = nullptr;
+  e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = enqueue_steps(g, order, bc, dt, tile, steps, g->cap);
+  e = hipStreamEndCapture(g->cap, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return le;
+  }
+  if (e != hipSuccess) return e;
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return e;
+  g->graphs.emplace(key, exec);
+  *out = exec;
+  return hipSuccess;
+}
+
+extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t nsteps) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  int rc = check_scheme(order, bc);
+  if (rc) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
+  if (nsteps < 0) return fail(NLSE_EINVAL, "nsteps must be >= 0");
+  const int* tile = g->tile[tile_slot(order)];
+  if (g->flags & NLSE_NO_GRAPH) {
+    hipError_t e = enqueue_steps(g, order, bc, dt, tile, nsteps, g->stream);
+    return e == hipSuccess ? NLSE_OK : hip_fail(e, "stage launch");
+  }
+  // chunks of kGraphSteps steps (and one shorter chunk), each a replayed graph
+  for (int64_t left = nsteps; left > 0;) {
+    const int k = (int)std::min<int64_t>(left, kGraphSteps);
+    hipGraphExec_t exec = nullptr;
+    hipError_t e = step_graph(g, order, bc, dt, tile, k, &exec);
+    if (e != hipSuccess) return hip_fail(e, "capturing the step graph");
+    e = hipGraphLaunch(exec, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    left -= k;
   }
   return NLSE_OK;
 }

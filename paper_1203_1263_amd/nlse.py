@@ -308,7 +308,7 @@ class Grid:
     """
 
     def __init__(self, psi, h: float, a: float, s: float, V=None, compensated: bool = False,
-                 stream=None, fused_pairs: bool = False):
+                 stream=None, fused_pairs: bool = False, graph: bool = True):
         import torch
         load_library()
         if not psi.is_cuda:
@@ -327,7 +327,8 @@ class Grid:
         self.ndim = psi.dim()
         self.dims = list(reversed(psi.shape)) + [1] * (3 - self.ndim)
         self.h, self.a, self.s = float(h), float(a), float(s)
-        self.flags = (NLSE_COMPENSATED if compensated else 0) | (NLSE_FUSED_PAIRS if fused_pairs else 0)
+        self.flags = ((NLSE_COMPENSATED if compensated else 0) | (NLSE_FUSED_PAIRS if fused_pairs else 0)
+                      | (0 if graph else NLSE_NO_GRAPH))
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         nbytes = nlse_workspace_bytes(self.ndim, self.dims, self.dtype, self.flags)
         self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=psi.device)

@@ -26,13 +26,13 @@ def pot_dev(V, dtype: str):
 
 
 def run_gpu(psi0, h, a, s, dt, nsteps, V=None, order=4, bc="msd", dtype="f32",
-            compensated=False, tile=None, autotune=False, return_grid=False, fused_pairs=False):
+            compensated=False, tile=None, autotune=False, return_grid=False, fused_pairs=False, graph=True):
     """Integrate on the GPU through the C ABI; returns the final field (numpy)."""
     import torch
     from paper_1203_1263_amd.nlse import Grid
     psi = to_dev(psi0, dtype)
     Vd = pot_dev(V, dtype)
-    g = Grid(psi, h, a, s, V=Vd, compensated=compensated, fused_pairs=fused_pairs)
+    g = Grid(psi, h, a, s, V=Vd, compensated=compensated, fused_pairs=fused_pairs, graph=graph)
     if tile is not None:
         g.set_tile(order, tile)
     if autotune:

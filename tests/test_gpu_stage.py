@@ -122,6 +122,49 @@ def test_fused_pairs_equal_four_passes(shape, bc, comp, withV, cz):
     assert rel_l2(fused, ref) < TOL["f32"]
 
 
+GRAPH_CASES = [((600,), "f32", 2, "dirichlet", False, False), ((37, 150), "f32", 4, "msd", True, False),
+               ((37, 150), "f64", 4, "dirichlet", False, False), ((11, 9, 70), "f32", 4, "msd", True, False),
+               ((11, 9, 70), "f32", 4, "msd", True, True), ((11, 9, 70), "f64", 2, "msd", False, False)]
+
+
+@pytest.mark.parametrize("shape,dtype,order,bc,comp,fused", GRAPH_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-{c[1]}-o{c[2]}-{c[3]}-c{int(c[4])}-f{int(c[5])}"
+                              for c in GRAPH_CASES])
+def test_graph_replay_equals_direct_launches(shape, dtype, order, bc, comp, fused):
+    """Step calls replay captured HIP graphs (chunks of 64 steps plus a
+    shorter one); the same calls with NLSE_NO_GRAPH launch every kernel
+    directly.  Both runs must agree bit for bit after every call, with eager
+    device work and host synchronisation between the replays, and after the
+    potential is replaced (which must drop the captured graphs)."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem(shape, 80 + len(shape))
+    V2 = 0.5 * V[::-1].copy()
+    dt = 0.5 * oracle.dt_max(len(shape), order, h, a)
+    runs = []
+    for graph in (True, False):
+        psi = to_dev(u, dtype)
+        g = Grid(psi, h, a, s, V=pot_dev(V, dtype), compensated=comp, fused_pairs=fused, graph=graph)
+        if fused:
+            g.set_tile(order, (32, 8, 5))
+        outs = []
+        for k, n in enumerate((130, 64, 3, 64)):
+            if k == 3:
+                g.set_potential(pot_dev(V2, dtype))
+            g.step(dt, n, order=order, bc=bc)
+            junk = torch.randn(1 << 16, device="cuda")
+            junk = (junk * 2).sum()  # eager work between replays
+            torch.cuda.synchronize()
+            outs.append(psi.cpu().numpy().copy())
+        g.close()
+        runs.append(outs)
+    for x, y in zip(*runs):
+        assert np.array_equal(x, y)
+    ref = oracle.rk4(u, h, a, s, dt, 197, V=V, order=order, bc=bc)
+    assert rel_l2(runs[0][2].astype(np.complex128), ref) < TOL[dtype]
+
+
 def test_run_twice_bitwise():
     u, V, h, a, s = smooth_problem((17, 23, 91), 3)
     dt = 0.5 * oracle.dt_max(3, 4, h, a)
