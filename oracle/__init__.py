@@ -11,7 +11,8 @@ Functions (each cites the passage of the paper it follows, in the C source):
 
 * :func:`dt_max` -- Eqs. stblincd / stblin2shoc.
 * :func:`rhs` -- F(Psi) of Eq. RK4 with the CD2 / 2SHOC Laplacian and the
-  Dirichlet / MSD boundary forms (Sec. "Boundary conditions").
+  Dirichlet / MSD / Laplacian-zero boundary forms (Sec. "Boundary
+  conditions").
 * :func:`laplacian` -- the scheme Laplacian alone at interior points.
 * :func:`rk4` -- classic RK4 in the ten-step ordering of Eq. RK4.
 * :func:`mass_energy` -- standard NLSE invariants (not defined by the paper).
@@ -32,7 +33,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nlse_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-BC = {"dirichlet": 0, "msd": 1}
+BC = {"dirichlet": 0, "msd": 1, "l0": 2}
 _lib = None
 
 

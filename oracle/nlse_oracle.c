@@ -15,7 +15,8 @@
  *     3d2shocs2), where step 1 stores D and step 2 combines D and Psi;
  *   - boundary conditions (Sec. "Boundary conditions"): Dirichlet, time form
  *     Eq. BCDdt and Laplacian form Eq. BCDlap; modulus-squared Dirichlet (MSD),
- *     time form Eq. msd and Laplacian form Eq. BCMSDlap;
+ *     time form Eq. msd and Laplacian form Eq. BCMSDlap; Laplacian-zero (L0),
+ *     time form Eq. BCL0dt and Laplacian form Eq. BCL0lap;
  *   - classic RK4 in the textbook ten-step ordering of Eq. RK4;
  *   - the linear stability bounds, Eqs. stblincd and stblin2shoc;
  *   - discrete mass and energy (the paper defines neither; the standard NLSE
@@ -41,6 +42,7 @@
 
 #define ORC_BC_DIRICHLET 0
 #define ORC_BC_MSD 1
+#define ORC_BC_L0 2
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -147,6 +149,7 @@ static void cd2_at(const grid_t *g, const double *u, long p, double out[2])
  * boundary points the Laplacian form of the boundary condition:
  *   Dirichlet (Eq. BCDlap): D_b = -(1/a) N_b Psi_b
  *   MSD (Eq. BCMSDlap):     D_b = [ Re(D_q / Psi_q) + (N_q - N_b)/a ] Psi_b,
+ *   L0 (Eq. BCL0lap):       D_b = 0,
  * where Im(i z) = Re(z) and D_q is the interior CD2 value at q. */
 static void compute_D(const grid_t *g, int bc, const double *u, double *D)
 {
@@ -167,6 +170,9 @@ static void compute_D(const grid_t *g, int bc, const double *u, double *D)
         if (bc == ORC_BC_DIRICHLET) {
             D[2 * p] = -(1.0 / g->a) * Nb * ur;
             D[2 * p + 1] = -(1.0 / g->a) * Nb * ui;
+        } else if (bc == ORC_BC_L0) {
+            D[2 * p] = 0.0;
+            D[2 * p + 1] = 0.0;
         } else {
             long q = inward(g, c);
             double Dq[2];
@@ -242,7 +248,8 @@ static void compute_L(const grid_t *g, int order, int bc, const double *u,
 /* F(Psi) = i [ a L + N Psi ] at interior points (definition under Eq. RK4;
  * split form Eq. fsplit).  Boundary points:
  *   Dirichlet (Eq. BCDdt): F_b = 0
- *   MSD (Eq. msd):         F_b = i Im(F_q / Psi_q) Psi_b. */
+ *   MSD (Eq. msd):         F_b = i Im(F_q / Psi_q) Psi_b
+ *   L0 (Eq. BCL0dt):       F_b = i N_b Psi_b. */
 static void compute_F(const grid_t *g, int order, int bc, const double *u,
                       double *F, double *L, double *D)
 {
@@ -268,6 +275,10 @@ static void compute_F(const grid_t *g, int order, int bc, const double *u,
         if (bc == ORC_BC_DIRICHLET) {
             F[2 * p] = 0.0;
             F[2 * p + 1] = 0.0;
+        } else if (bc == ORC_BC_L0) {
+            double Nb = nl(g, u, p);
+            F[2 * p] = -Nb * u[2 * p + 1]; /* i * N_b * Psi_b */
+            F[2 * p + 1] = Nb * u[2 * p];
         } else {
             long q = inward(g, c);
             double w = im_ratio(F[2 * q], F[2 * q + 1], u[2 * q], u[2 * q + 1]);
@@ -281,7 +292,7 @@ static void compute_F(const grid_t *g, int order, int bc, const double *u,
 static int check_scheme(int order, int bc)
 {
     if (order != 2 && order != 4) return ORC_EINVAL;
-    if (bc != ORC_BC_DIRICHLET && bc != ORC_BC_MSD) return ORC_EINVAL;
+    if (bc != ORC_BC_DIRICHLET && bc != ORC_BC_MSD && bc != ORC_BC_L0) return ORC_EINVAL;
     return ORC_OK;
 }
 

@@ -4,6 +4,7 @@ None of these tests compares the oracle with itself or retypes its formulas:
 each checks it against a printed value, a closed form, an exact discrete
 solution, an invariant, a convergence rate, or an independent formula.
 """
+import ctypes
 import math
 import os
 
@@ -70,9 +71,13 @@ def _lam(kappa_h, order):
 
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 @pytest.mark.parametrize("order", [2, 4])
-def test_dispersion_sine_dirichlet(ndim, order):
-    """s = V = 0, zero Dirichlet boundary: a product of sines is an exact
-    eigenmode of the scheme, so RK4 gives psi^n = R(i a k lambda)^n psi^0."""
+@pytest.mark.parametrize("bc", ["dirichlet", "l0"])
+def test_dispersion_sine_dirichlet(ndim, order, bc):
+    """s = V = 0, zero boundary values: a product of sines is an exact
+    eigenmode of the scheme, so RK4 gives psi^n = R(i a k lambda)^n psi^0.
+    With s = V = 0 the Laplacian-zero condition (Eqs. BCL0dt, BCL0lap) gives
+    F_b = 0 and D_b = 0 as Dirichlet does, and the sine profile is odd about
+    every boundary point, so D_b = 0 is also what CD2 would give there."""
     shape = {1: (40,), 2: (17, 23), 3: (9, 11, 13)}[ndim]
     h, a = 0.2, 0.8
     modes = {1: (3,), 2: (2, 5), 3: (1, 3, 4)}[ndim]
@@ -90,7 +95,7 @@ def test_dispersion_sine_dirichlet(ndim, order):
     psi = psi * (0.3 + 0.4j)
     dt = 0.7 * oracle.dt_max(ndim, order, h, a)
     nsteps = 20
-    out = oracle.rk4(psi, h, a, 0.0, dt, nsteps, order=order, bc="dirichlet")
+    out = oracle.rk4(psi, h, a, 0.0, dt, nsteps, order=order, bc=bc)
     expect = R4(1j * a * dt * lam) ** nsteps * psi
     assert np.max(np.abs(out - expect)) < 1e-13
 
@@ -212,23 +217,109 @@ def test_stationary_state_is_fixed_point(ndim, order, bc):
     assert np.max(np.abs(out2 - psi)) > 1e-4
 
 
+def _scalar_rk4(y, s, v, dt, n):
+    """n textbook RK4 steps of the scalar ODE psi' = i (s|psi|^2 - v) psi
+    (numpy-broadcast over y and v)."""
+    f = lambda z: 1j * (s * np.abs(z) ** 2 - v) * z
+    for _ in range(n):
+        k1 = f(y); k2 = f(y + dt / 2 * k1); k3 = f(y + dt / 2 * k2); k4 = f(y + dt * k3)
+        y = y + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    return y
+
+
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 @pytest.mark.parametrize("order", [2, 4])
-def test_uniform_field_msd_follows_scalar_rk4(ndim, order):
-    """A uniform field under MSD with uniform V stays uniform; each point
-    follows the scalar RK4 recurrence of psi' = i (s|psi|^2 - V) psi."""
+@pytest.mark.parametrize("bc", ["msd", "l0"])
+def test_uniform_field_msd_follows_scalar_rk4(ndim, order, bc):
+    """A uniform field under MSD or L0 with uniform V stays uniform; each point
+    follows the scalar RK4 recurrence of psi' = i (s|psi|^2 - V) psi.  For
+    2SHOC this needs D_b = 0 at the boundary: the Dirichlet form
+    -(1/a) N_b psi_b is not zero here and would bend the first interior
+    layer."""
     shape = {1: (12,), 2: (7, 9), 3: (5, 6, 7)}[ndim]
     h, a, s, v = 0.2, 1.0, 0.8, 0.35
     psi0 = 0.9 - 0.5j
     V = np.full(shape, v)
     dt = 0.01
-    out = oracle.rk4(np.full(shape, psi0), h, a, s, dt, 30, V=V, order=order, bc="msd")
-    y = psi0
-    f = lambda z: 1j * (s * abs(z) ** 2 - v) * z
-    for _ in range(30):
-        k1 = f(y); k2 = f(y + dt / 2 * k1); k3 = f(y + dt / 2 * k2); k4 = f(y + dt * k3)
-        y = y + dt / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    out = oracle.rk4(np.full(shape, psi0), h, a, s, dt, 30, V=V, order=order, bc=bc)
+    y = _scalar_rk4(psi0, s, v, dt, 30)
     assert np.max(np.abs(out - y)) < 1e-13
+
+
+def _boundary_mask(shape):
+    m = np.zeros(shape, dtype=bool)
+    for ax in range(len(shape)):
+        idx = [slice(None)] * len(shape)
+        idx[ax] = 0
+        m[tuple(idx)] = True
+        idx[ax] = -1
+        m[tuple(idx)] = True
+    return m
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("order", [2, 4])
+def test_l0_boundary_points_follow_their_own_scalar_rk4(ndim, order):
+    """Under L0 (Eq. BCL0dt) the time derivative of a boundary point depends
+    on that point alone, so for any interior field and any potential every
+    boundary point follows the scalar RK4 recurrence with its own V_b.
+    Dirichlet (frozen) and MSD (coupled to the inward neighbour) both fail
+    this, which the test checks too."""
+    shape = {1: (14,), 2: (8, 11), 3: (6, 7, 9)}[ndim]
+    h, a, s = 0.3, 0.8, -1.1
+    u = 1.5 + 0.4 * wl.random_field(shape, 21 + ndim, smooth=1.0)  # |u| > 0 keeps MSD finite
+    V = 0.5 * wl.random_field(shape, 21 + ndim, stream=1).real
+    dt, n = 0.4 * oracle.dt_max(ndim, order, h, a), 12
+    b = _boundary_mask(shape)
+    expect = _scalar_rk4(u[b], s, V[b], dt, n)
+    out = oracle.rk4(u, h, a, s, dt, n, V=V, order=order, bc="l0")
+    assert np.max(np.abs(out[b] - expect)) < 1e-13
+    assert np.max(np.abs(out[~b] - u[~b])) > 1e-3  # the interior does move
+    for other in ("dirichlet", "msd"):
+        o = oracle.rk4(u, h, a, s, dt, n, V=V, order=order, bc=other)
+        assert np.max(np.abs(o[b] - expect)) > 1e-4
+
+
+def test_l0_2shoc_1d_equals_wide_stencil_on_odd_reflection():
+    """1D 2SHOC with L0 (D_b = 0, Eq. BCL0lap): extending the field by odd
+    reflection about the boundary point, u_{-k} = 2u_0 - u_k, makes the CD2
+    value at the boundary exactly zero, so the L0 Laplacian at every interior
+    point equals the interior 2SHOC of the extended field, which is the wide
+    fourth-order stencil (-u_{+-2}/12 + 4/3 u_{+-1} - 5/2 u)/h^2."""
+    n, h = 17, 0.37
+    u = wl.random_field((n,), 31)
+    L = oracle.laplacian(u, h, a=0.9, s=0.4, order=4, bc="l0")
+    ext = np.concatenate([2 * u[0] - u[2:0:-1], u, 2 * u[-1] - u[-2:-4:-1]])  # 2 ghost points each side
+    i = np.arange(1, n - 1) + 2
+    wide = (-(ext[i + 2] + ext[i - 2]) / 12 + 4 / 3 * (ext[i + 1] + ext[i - 1]) - 2.5 * ext[i]) / h ** 2
+    assert np.max(np.abs(L[1:-1] - wide)) < 1e-10 * np.max(np.abs(wide))
+    # the MSD form of D_b gives a different first interior layer
+    Lm = oracle.laplacian(u, h, a=0.9, s=0.4, order=4, bc="msd")
+    assert np.max(np.abs(Lm[1:-1] - wide)) > 1e-3
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_l0_stationary_dark_soliton(order):
+    """The black soliton tanh(x/sqrt(2a)) e^{-it} (Eq. soliton with zero
+    speed, s = -1) has a vanishing Laplacian far from its core, where its
+    boundary values obey Eq. BCL0dt up to e^{-2L/sqrt(2a)}.  With L0 the
+    error after t = 1 is the discretisation error, falling as h^2 (CD2) or
+    h^4 (2SHOC); Dirichlet freezes the rotating boundary values and does far
+    worse."""
+    a, s, T = 1.0, -1.0, 1.0
+
+    def err(h, bc):
+        x = np.arange(-30, 30 + h / 2, h)
+        ex0 = wl.dark_soliton1d_exact(x, 0.0, a=a, s=s, c=0.0)
+        exT = wl.dark_soliton1d_exact(x, T, a=a, s=s, c=0.0)
+        dt = 0.8 * oracle.dt_max(1, order, h, a)
+        nst = int(math.ceil(T / dt))
+        out = oracle.rk4(ex0, h, a, s, T / nst, nst, order=order, bc=bc)
+        return np.linalg.norm(out - exT) / np.linalg.norm(exT)
+
+    e1, e2 = err(0.2, "l0"), err(0.1, "l0")
+    assert math.log2(e1 / e2) == pytest.approx(order, abs=0.15)
+    assert err(0.2, "dirichlet") > 10 * e1
 
 
 def test_dirichlet_boundary_frozen_and_rhs_zero():
@@ -366,3 +457,8 @@ def test_oracle_rejects_bad_arguments():
         oracle.rk4(np.zeros(8, complex), -0.1, 1.0, 1.0, 1e-3, 1)
     with pytest.raises(ValueError):
         oracle.rk4(np.zeros(8, complex), 0.1, 1.0, 1.0, 1e-3, 1, order=3)
+    lib = oracle._load()
+    u = np.zeros(16)
+    n = (ctypes.c_long * 3)(8, 1, 1)
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.orc_rk4(1, n, 0.1, 1.0, 1.0, None, 2, 3, 1e-3, 1, u.ctypes.data_as(dp)) != 0  # bc 3 unknown
