@@ -57,7 +57,16 @@ typedef enum {
 
 enum { NLSE_F32 = 0, NLSE_F64 = 1 };               /* element type            */
 enum { NLSE_CD2 = 2, NLSE_2SHOC = 4 };              /* Laplacian order         */
-enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1 };    /* boundary condition      */
+/* Boundary conditions (Sec. "Boundary conditions"), each applied through its
+ * time form to F at boundary points and, for 2SHOC, through its Laplacian
+ * form to the step-1 value D at boundary points:
+ *   NLSE_BC_DIRICHLET  Eqs. BCDdt / BCDlap: F_b = 0, D_b = -(1/a) N_b Psi_b
+ *   NLSE_BC_MSD        Eqs. msd / BCMSDlap: F_b from the inward neighbour q,
+ *                      F_b = i Im(F_q/Psi_q) Psi_b (q one step inward on
+ *                      every boundary axis; a zero Psi_q gives 0)
+ *   NLSE_BC_L0         Eqs. BCL0dt / BCL0lap: F_b = i N_b Psi_b, D_b = 0
+ * with N = s|Psi|^2 - V.  Boundary points: an index 0 or N_d-1 on any axis. */
+enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1, NLSE_BC_L0 = 2 };
 
 /* Grid / batch flags. */
 #define NLSE_COMPENSATED 0x1u /* FP32 only: keep Psi as hi+lo pair, RK4
@@ -120,7 +129,8 @@ int nlse_set_potential(nlse_grid *g, const void *V_dev);
  * `order` (NLSE_CD2 or NLSE_2SHOC) and boundary condition `bc`.  Each step is
  * four fused stage kernels (stencil, boundary update and RK4 accumulation in
  * one pass each); grids created with NLSE_FUSED_PAIRS run two launches per
- * step instead (stages 1+2 and 3+4), with the same bits.  Unless the grid
+ * step instead (stages 1+2 and 3+4), with the same bits (NLSE_BC_L0 always
+ * takes the four single-stage kernels).  Unless the grid
  * has NLSE_NO_GRAPH, the launches of up to 64 steps are captured once per
  * (order, bc, dt, tile, step count) into a HIP graph that is replayed
  * (setting a different potential drops the captured graphs).
@@ -175,7 +185,7 @@ typedef struct {
     int ndim;            /* must be 2                                       */
     int64_t dims[3];     /* {Nx, Ny, 1}, Nx, Ny >= 3                        */
     double h, a, s, dt;  /* spacing, dispersion (> 0), nonlinearity, step   */
-    int order, bc;       /* NLSE_CD2 / NLSE_2SHOC, NLSE_BC_DIRICHLET / _MSD  */
+    int order, bc;       /* NLSE_CD2 / NLSE_2SHOC, NLSE_BC_DIRICHLET / _MSD / _L0 */
     int64_t psi_offset;  /* first complex element of this field in psi_pool */
     int64_t v_offset;    /* first real element of V in v_pool, -1: V == 0   */
 } nlse_sim_desc;

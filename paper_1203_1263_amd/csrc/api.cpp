@@ -282,8 +282,8 @@ extern "C" int nlse_set_potential(nlse_grid* g, const void* V_dev) {
 
 static int check_scheme(int order, int bc) {
   if (order != NLSE_CD2 && order != NLSE_2SHOC) return fail(NLSE_EINVAL, "order must be 2 (CD2) or 4 (2SHOC)");
-  if (bc != NLSE_BC_DIRICHLET && bc != NLSE_BC_MSD)
-    return fail(NLSE_EINVAL, "bc must be NLSE_BC_DIRICHLET or NLSE_BC_MSD");
+  if (bc != NLSE_BC_DIRICHLET && bc != NLSE_BC_MSD && bc != NLSE_BC_L0)
+    return fail(NLSE_EINVAL, "bc must be NLSE_BC_DIRICHLET, NLSE_BC_MSD or NLSE_BC_L0");
   return NLSE_OK;
 }
 
@@ -339,7 +339,7 @@ static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt,
 static hipError_t enqueue_steps(const nlse_grid* g, int order, int bc, double dt, const int tile[3], int64_t nsteps,
                                 hipStream_t st) {
   int64_t left = nsteps;
-  if (fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 && tile[1] == 8) {
+  if (bc != NLSE_BC_L0 && fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 && tile[1] == 8) {
     // Pairs of steps Psi -> workspace -> Psi (the fused launches cannot
     // update Psi in place); an odd last step takes the four-pass kernels,
     // which give the same bits.
@@ -629,7 +629,7 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   float best = 1e30f;
   std::array<int, 3> best_t = cands[0];
   const int reps = g->shape.npts > (1 << 20) ? 5 : 20;
-  const bool fused = fused_eligible(g->shape, g->dtype, g->flags, order);
+  const bool fused = bc != NLSE_BC_L0 && fused_eligible(g->shape, g->dtype, g->flags, order);
   for (auto& t : cands) {
     for (int d = 0; d < 3; ++d) L.tile[d] = t[d];
     auto run = [&](int n) -> hipError_t {

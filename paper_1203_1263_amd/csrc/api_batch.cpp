@@ -47,7 +47,8 @@ int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, in
       return nlse_fail(NLSE_EINVAL, "problem %d: need h > 0, a > 0, finite s", j);
     if (!(d.dt > 0) || !std::isfinite(d.dt)) return nlse_fail(NLSE_EINVAL, "problem %d: dt must be > 0", j);
     if (d.order != NLSE_CD2 && d.order != NLSE_2SHOC) return nlse_fail(NLSE_EINVAL, "problem %d: bad order", j);
-    if (d.bc != NLSE_BC_DIRICHLET && d.bc != NLSE_BC_MSD) return nlse_fail(NLSE_EINVAL, "problem %d: bad bc", j);
+    if (d.bc != NLSE_BC_DIRICHLET && d.bc != NLSE_BC_MSD && d.bc != NLSE_BC_L0)
+      return nlse_fail(NLSE_EINVAL, "problem %d: bad bc", j);
     if (d.psi_offset < 0 || d.v_offset < -1) return nlse_fail(NLSE_EINVAL, "problem %d: bad offsets", j);
     const int64_t n = d.dims[0] * d.dims[1];
     tot += n;

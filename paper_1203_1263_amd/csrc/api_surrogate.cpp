@@ -335,7 +335,7 @@ extern "C" int nlse_surrogate_advance(nlse_surrogate* m, nlse_grid* g, int order
     return nlse_fail(NLSE_EINVAL, "the grid must be a 2D FP32 field of the model's H x W");
   if (gst != (void*)m->stream) return nlse_fail(NLSE_EINVAL, "grid and model must share a stream");
   if (nblocks < 0 || !(drift_tol >= 0)) return nlse_fail(NLSE_EINVAL, "bad nblocks / drift_tol");
-  if (bc != NLSE_BC_DIRICHLET && bc != NLSE_BC_MSD) return nlse_fail(NLSE_EINVAL, "bad bc");
+  if (bc != NLSE_BC_DIRICHLET && bc != NLSE_BC_MSD && bc != NLSE_BC_L0) return nlse_fail(NLSE_EINVAL, "bad bc");
   void* xin = m->work + m->lay.scratch;
   const size_t bytes = (size_t)m->H * m->W * 8;
   int64_t fb = 0;

@@ -160,11 +160,15 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
     if (I.order == 4) {
       if (I.bc == kMSD)
         tile2d_compute<T, 4, kMSD, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+      else if (I.bc == kL0)
+        tile2d_compute<T, 4, kL0, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
       else
         tile2d_compute<T, 4, kDirichlet, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
     } else {
       if (I.bc == kMSD)
         tile2d_compute<T, 2, kMSD, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
+      else if (I.bc == kL0)
+        tile2d_compute<T, 2, kL0, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
       else
         tile2d_compute<T, 2, kDirichlet, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
     }

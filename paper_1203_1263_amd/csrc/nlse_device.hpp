@@ -13,7 +13,7 @@
 
 namespace nlse {
 
-enum { kDirichlet = 0, kMSD = 1 };
+enum { kDirichlet = 0, kMSD = 1, kL0 = 2 };
 
 // Interleaved complex value; 8-byte (FP32) / 16-byte (FP64) aligned so a
 // lane moves one point with a single vector memory instruction.
@@ -68,6 +68,13 @@ __device__ __forceinline__ cpx<T> msd_rhs(cpx<T> Fq, cpx<T> uq, cpx<T> ub) {
   T m = fmaT(uq.re, uq.re, uq.im * uq.im);
   T w = (m == T(0)) ? T(0) : fmaT(Fq.im, uq.re, -(Fq.re * uq.im)) / m;
   return mk<T>(-(w * ub.im), w * ub.re);
+}
+
+// Laplacian-zero time form (Eq. BCL0dt): F_b = i N_b u_b.  Its Laplacian
+// form (Eq. BCL0lap) is D_b = 0.
+template <typename T>
+__device__ __forceinline__ cpx<T> l0_rhs(cpx<T> ub, T Nb) {
+  return mk<T>(-(Nb * ub.im), Nb * ub.re);
 }
 
 // Dirichlet Laplacian form (Eq. BCDlap): D_b = -(1/a) N_b u_b.

@@ -3,7 +3,7 @@
 //   M = h^d sum |Psi|^2
 //   E = h^d [ sum_interior -a Re(conj(Psi) L Psi) + sum ( V|Psi|^2 - (s/2)|Psi|^4 ) ]
 // with L the scheme Laplacian (CD2, or 2SHOC reading the boundary D of the
-// chosen condition, Eqs. BCDlap / BCMSDlap).  Stored values are promoted to
+// chosen condition, Eqs. BCDlap / BCMSDlap / BCL0lap).  Stored values are promoted to
 // FP64 and every operation below runs in FP64.
 //
 // Determinism: workgroup b always reduces the fixed index range
@@ -69,6 +69,7 @@ __device__ __forceinline__ double nl_d(const View<T>& g, cpx<double> u, double v
 template <typename T>
 __device__ cpx<double> D_at(const View<T>& g, int bc, const int c[3]) {
   if (!on_bnd(g, c)) return cd2_at(g, c);
+  if (bc == kL0) return mk<double>(0.0, 0.0);  // Eq. BCL0lap
   cpx<double> ub = ldd(g, c);
   double Nb = nl_d(g, ub, vd(g, c));
   if (bc == kDirichlet) {

@@ -2,7 +2,8 @@
 // stage input of a 256-point tile plus halo is staged in LDS, the 2SHOC
 // temporary D (Eq. 2shoc1d) is formed in LDS on the tile plus one point each
 // side, the Laplacian (CD2, or Eq. 2shoc1d2), F, the boundary forms (Eqs.
-// BCDdt, BCDlap, msd, BCMSDlap) and the stage accumulation follow, and only
+// BCDdt, BCDlap, msd, BCMSDlap, BCL0dt, BCL0lap) and the stage accumulation
+// follow, and only
 // the RK4 arrays touch HBM.
 #include "stage_common.hpp"
 
@@ -25,8 +26,9 @@ __global__ __launch_bounds__(TX) void stage1d_kernel(StageArgs<T> A) {
   const bool store = valid && x >= t * TX;
   const int xc = valid ? x : nx - 1;  // clamped: every load is in bounds
   // MSD boundary points evaluate F at their interior neighbour q themselves
+  // (L0 needs only the point's own values)
   const bool bnd = valid && (x == 0 || x == nx - 1);
-  const int qlx = lx + (bnd ? inward(x, nx) : 0);
+  const int qlx = lx + ((BC != kL0 && bnd) ? inward(x, nx) : 0);
   const Phys<T>& ph = A.ph;
 
   Own<T> own;
@@ -51,7 +53,7 @@ __global__ __launch_bounds__(TX) void stage1d_kernel(StageArgs<T> A) {
           add_diff(sr, si, sU[b + 1], c);
           add_diff(sr, si, sU[b - 1], c);
           d = mk<T>(sr * ph.inv_h2, si * ph.inv_h2);
-        } else {
+        } else if constexpr (BC != kL0) {  // L0: D_b = 0
           T Nb = nlin(ph, c, vload(A, gx));
           if (BC == kDirichlet) {
             d = dirichlet_lap(ph, c, Nb);
@@ -91,7 +93,11 @@ __global__ __launch_bounds__(TX) void stage1d_kernel(StageArgs<T> A) {
     Kq = rhs(ph, L, uq, nlin(ph, uq, vq));
   }
   cpx<T> K = Kq;
-  if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
+  if (bnd) {
+    if constexpr (BC == kMSD) K = msd_rhs(Kq, uq, u0);
+    else if constexpr (BC == kL0) K = l0_rhs(u0, nlin(ph, u0, vq));
+    else K = czero<T>();
+  }
   if (store) stage_update<T, STAGE, COMP>(A, x, u0, K, own);
 }
 

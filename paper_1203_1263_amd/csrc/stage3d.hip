@@ -66,7 +66,9 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   const int64_t cidx = (int64_t)min(y, ny - 1) * nx + min(x, nx - 1);  // clamped own column
   // interior column whose F this thread evaluates: its own, or for a
   // boundary column the MSD neighbour one step inward on each boundary axis
-  const int qlx = lx + (bnd ? inward(x, nx) : 0), qly = ly + (bnd ? inward(y, ny) : 0);
+  // (L0 needs only the point's own values)
+  const bool shift = BC != kL0 && bnd;
+  const int qlx = lx + (shift ? inward(x, nx) : 0), qly = ly + (shift ? inward(y, ny) : 0);
   const int64_t qidx = valid ? (int64_t)(y0 + qly) * nx + (x0 + qlx) : cidx;
   const int zb = 1 + zc * cz;
   const int ze = min(zb + cz, nz - 1);
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
       if (din[k]) {
         if (!zbnd && dint[k]) {
           d = cd2(zp, dbi[k]);
-        } else {
+        } else if constexpr (BC != kL0) {  // L0: D_b = 0
           const StageArgs<T> Pz = plane_args(zp);
           cpx<T> ub = slot(zp)[dbi[k]];
           T Nb = nlin(ph, ub, vload(Pz, dgo[k]));
@@ -208,7 +210,9 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     if (zb - 1 == 0) {
       cpx<T> ub = slot(0)[ci];
       T Nb = nlin(ph, ub, vload(A, qidx));
-      if (BC == kDirichlet) {
+      if (BC == kL0) {
+        dm = czero<T>();
+      } else if (BC == kDirichlet) {
         dm = dirichlet_lap(ph, ub, Nb);
       } else {
         cpx<T> uq = slot(1)[ci];
@@ -278,7 +282,11 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     }
     const cpx<T> Kq = rhs(ph, L, uq, nlin(ph, uq, cur.vq));
     cpx<T> K = Kq;
-    if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
+    if (bnd) {
+      if constexpr (BC == kMSD) K = msd_rhs(Kq, uq, u0);
+      else if constexpr (BC == kL0) K = l0_rhs(u0, nlin(ph, u0, cur.vq));
+      else K = czero<T>();
+    }
     if (store) stage_update<T, STAGE, COMP, STREAM>(plane_args(z), c32, u0, K, cur.own);
     // boundary planes: F_b from the interior neighbour in plane 1 / nz-2
     if (z == 1 || z == nz - 2) {
@@ -289,7 +297,9 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
         Own<T> o;
         load_own<T, STAGE, COMP, STREAM>(Pb, c32, o);
         const cpx<T> ub = slot(zbp)[oi];
-        const cpx<T> Kb = (BC == kMSD) ? msd_rhs(Kq, uq, ub) : czero<T>();
+        cpx<T> Kb = czero<T>();
+        if constexpr (BC == kMSD) Kb = msd_rhs(Kq, uq, ub);
+        else if constexpr (BC == kL0) Kb = l0_rhs(ub, nlin(ph, ub, vload(Pb, c32)));
         if (store) stage_update<T, STAGE, COMP, STREAM>(Pb, c32, ub, Kb, o);
       }
     }

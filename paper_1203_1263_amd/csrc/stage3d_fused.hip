@@ -550,8 +550,8 @@ hipError_t pair1(const nlse::StageLaunch& L, nlse::FusedArgs A, void* psi, const
 }
 
 bool fused_ok(const nlse::StageLaunch& L) {
-  return L.ndim == 3 && L.dtype == 0 && L.order == 4 && L.tile[0] == nlse::fz::TX && L.tile[1] == nlse::fz::TY &&
-         L.tile[2] >= 1 && L.n[2] >= 3;
+  return L.ndim == 3 && L.dtype == 0 && L.order == 4 && (L.bc == nlse::kDirichlet || L.bc == nlse::kMSD) &&
+         L.tile[0] == nlse::fz::TX && L.tile[1] == nlse::fz::TY && L.tile[2] >= 1 && L.n[2] >= 3;
 }
 
 }  // namespace

@@ -82,16 +82,21 @@ hipError_t dispatch_stage(const StageLaunch& L, hipStream_t st) {
 
 template <template <typename, int, int, int, int> class F>
 hipError_t dispatch_all(const StageLaunch& L, hipStream_t st) {
-  const int k = (L.dtype ? 4 : 0) + (L.order == 4 ? 2 : 0) + (L.bc == kMSD ? 1 : 0);
+  if (L.bc != kDirichlet && L.bc != kMSD && L.bc != kL0) return hipErrorInvalidValue;
+  const int k = (L.dtype ? 6 : 0) + (L.order == 4 ? 3 : 0) + L.bc;
   switch (k) {
     case 0: return dispatch_stage<float, 2, kDirichlet, F>(L, st);
     case 1: return dispatch_stage<float, 2, kMSD, F>(L, st);
-    case 2: return dispatch_stage<float, 4, kDirichlet, F>(L, st);
-    case 3: return dispatch_stage<float, 4, kMSD, F>(L, st);
-    case 4: return dispatch_stage<double, 2, kDirichlet, F>(L, st);
-    case 5: return dispatch_stage<double, 2, kMSD, F>(L, st);
-    case 6: return dispatch_stage<double, 4, kDirichlet, F>(L, st);
-    default: return dispatch_stage<double, 4, kMSD, F>(L, st);
+    case 2: return dispatch_stage<float, 2, kL0, F>(L, st);
+    case 3: return dispatch_stage<float, 4, kDirichlet, F>(L, st);
+    case 4: return dispatch_stage<float, 4, kMSD, F>(L, st);
+    case 5: return dispatch_stage<float, 4, kL0, F>(L, st);
+    case 6: return dispatch_stage<double, 2, kDirichlet, F>(L, st);
+    case 7: return dispatch_stage<double, 2, kMSD, F>(L, st);
+    case 8: return dispatch_stage<double, 2, kL0, F>(L, st);
+    case 9: return dispatch_stage<double, 4, kDirichlet, F>(L, st);
+    case 10: return dispatch_stage<double, 4, kMSD, F>(L, st);
+    default: return dispatch_stage<double, 4, kL0, F>(L, st);
   }
 }
 

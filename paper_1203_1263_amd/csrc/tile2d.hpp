@@ -90,8 +90,10 @@ __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, in
   const bool store = valid && x >= tx * TX && y >= ty * TY;
   const int64_t idx = (int64_t)min(y, ny - 1) * nx + min(x, nx - 1);  // clamped
   // MSD boundary points evaluate F at their interior neighbour q themselves
+  // (L0 needs only the point's own values)
   const bool bnd = valid && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1);
-  const int qlx = lx + (bnd ? inward(x, nx) : 0), qly = ly + (bnd ? inward(y, ny) : 0);
+  const bool shift = BC != kL0 && bnd;
+  const int qlx = lx + (shift ? inward(x, nx) : 0), qly = ly + (shift ? inward(y, ny) : 0);
   const Phys<T>& ph = A.ph;
 
 #pragma unroll
@@ -124,7 +126,7 @@ __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, in
         int qx = inward(gx, nx), qy = inward(gy, ny);
         if (qx == 0 && qy == 0) {
           d = cd2(br, bc);
-        } else {
+        } else if constexpr (BC != kL0) {  // L0: D_b = 0
           cpx<T> ub = U(br, bc);
           T Nb = nlin(ph, ub, Vb(br, bc));
           if (BC == kDirichlet) {
@@ -167,7 +169,11 @@ __device__ __forceinline__ void tile2d_compute(const StageArgs<T>& A, int tx, in
     Kq = rhs(ph, L, uq, nlin(ph, uq, Vb(qly + H, qlx + H)));
   }
   cpx<T> K = Kq;
-  if (bnd) K = (BC == kMSD) ? msd_rhs(Kq, uq, u0) : czero<T>();
+  if (bnd) {
+    if constexpr (BC == kMSD) K = msd_rhs(Kq, uq, u0);
+    else if constexpr (BC == kL0) K = l0_rhs(u0, nlin(ph, u0, Vb(ly + H, lx + H)));
+    else K = czero<T>();
+  }
   if (store) stage_update<T, STAGE, COMP, STREAM>(A, idx, u0, K, R.own);
 }
 

@@ -26,12 +26,12 @@ NLSE_EUNSTABLE = -4
 NLSE_EUNSUPPORTED = -5
 NLSE_F32, NLSE_F64 = 0, 1
 NLSE_CD2, NLSE_2SHOC = 2, 4
-NLSE_BC_DIRICHLET, NLSE_BC_MSD = 0, 1
+NLSE_BC_DIRICHLET, NLSE_BC_MSD, NLSE_BC_L0 = 0, 1, 2
 NLSE_COMPENSATED = 0x1
 NLSE_NO_GRAPH = 0x2
 NLSE_FUSED_PAIRS = 0x4
 
-BC = {"dirichlet": NLSE_BC_DIRICHLET, "msd": NLSE_BC_MSD}
+BC = {"dirichlet": NLSE_BC_DIRICHLET, "msd": NLSE_BC_MSD, "l0": NLSE_BC_L0}
 
 
 class SimDesc(ctypes.Structure):

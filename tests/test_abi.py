@@ -119,7 +119,8 @@ def test_batch_workspace_and_validation():
     assert n >= 3 * 8 * (4096 + 8192)
     for bad, code in ((dict(ndim=3), nlse.NLSE_EUNSUPPORTED), (dict(dims=(2, 64, 1)), nlse.NLSE_EINVAL),
                       (dict(order=3), nlse.NLSE_EINVAL), (dict(dt=0.0), nlse.NLSE_EINVAL),
-                      (dict(a=-1.0), nlse.NLSE_EINVAL), (dict(v_offset=-2), nlse.NLSE_EINVAL)):
+                      (dict(a=-1.0), nlse.NLSE_EINVAL), (dict(v_offset=-2), nlse.NLSE_EINVAL),
+                      (dict(bc=3), nlse.NLSE_EINVAL)):
         with pytest.raises(nlse.NLSEError) as e:
             nlse.nlse_batch_workspace_bytes([_desc(**bad)], nlse.NLSE_F32)
         assert e.value.code == code

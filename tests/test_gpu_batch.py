@@ -39,7 +39,7 @@ def small_batch(seed=5):
         u = 1.2 + 0.25 * wl.random_field((ny, nx), 300 + k, smooth=2.0)
         V = 0.3 * wl.random_field((ny, nx), 300 + k, stream=1, smooth=3.0).real if k % 3 else None
         order = (2, 4)[k % 2]
-        bc = ("dirichlet", "msd")[(k // 2) % 2]
+        bc = ("dirichlet", "msd", "l0")[(k // 2) % 3]
         h, a, s = float(g.uniform(0.2, 0.4)), float(g.uniform(0.5, 1.0)), float(g.choice([-1.0, 0.2]))
         probs.append(P(u, h, a, s, V, order, bc))
         dts.append(0.5 * oracle.dt_max(2, order, h, a))

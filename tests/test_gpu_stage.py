@@ -49,7 +49,7 @@ SHAPES = {
     3: [(21, 13, 70), (3, 3, 3), (11, 5, 66), (6, 9, 8)],
 }
 CASES = [(nd, shp, order, bc) for nd in (1, 2, 3) for shp in SHAPES[nd] for order in (2, 4)
-         for bc in ("dirichlet", "msd")]
+         for bc in ("dirichlet", "msd", "l0")]
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -86,7 +86,7 @@ def _tiles(nd):
 
 
 @pytest.mark.parametrize("nd", [2, 3])
-@pytest.mark.parametrize("order,bc", [(2, "dirichlet"), (4, "msd")])
+@pytest.mark.parametrize("order,bc", [(2, "dirichlet"), (4, "msd"), (4, "l0")])
 def test_tile_shape_bit_invariance(nd, order, bc):
     """Every tile shape the autotuner may choose yields identical bits."""
     shape = (70, 131) if nd == 2 else (19, 21, 133)
@@ -101,7 +101,8 @@ def test_tile_shape_bit_invariance(nd, order, bc):
 FUSED_CASES = [((19, 21, 133), "msd", True, True, 16), ((19, 21, 133), "dirichlet", False, True, 5),
                ((3, 3, 3), "msd", True, True, 1), ((4, 9, 40), "msd", False, False, 1),
                ((5, 10, 33), "dirichlet", True, True, 2), ((12, 17, 31), "msd", True, False, 3),
-               ((40, 12, 70), "msd", True, True, 7), ((40, 12, 70), "msd", False, True, 38)]
+               ((40, 12, 70), "msd", True, True, 7), ((40, 12, 70), "msd", False, True, 38),
+               ((19, 21, 133), "l0", True, True, 16)]
 
 
 @pytest.mark.parametrize("shape,bc,comp,withV,cz", FUSED_CASES,
@@ -111,7 +112,8 @@ def test_fused_pairs_equal_four_passes(shape, bc, comp, withV, cz):
     """3D FP32 2SHOC with NLSE_FUSED_PAIRS: the two fused launches per step
     (stages 1+2, 3+4; an odd last step takes four passes) give the bits of
     the four single-stage launches, for ragged shapes, tiny nz, every z-chunk
-    length and both boundary conditions."""
+    length and both boundary conditions the fused kernels implement (L0
+    always takes the four single-stage kernels)."""
     u, V, h, a, s = smooth_problem(shape, 60 + cz, V=withV)
     dt = 0.5 * oracle.dt_max(3, 4, h, a)
     fused = run_gpu(u, h, a, s, dt, 7, V=V, order=4, bc=bc, dtype="f32", compensated=comp, tile=(32, 8, cz),
@@ -219,7 +221,7 @@ def test_checkpoint_restore_bitwise():
 # ---------------------------------------------------------------- mass / energy
 
 @pytest.mark.parametrize("nd,shape", [(1, (600,)), (2, (37, 150)), (3, (21, 13, 70))])
-@pytest.mark.parametrize("order,bc", [(2, "dirichlet"), (4, "msd"), (4, "dirichlet")])
+@pytest.mark.parametrize("order,bc", [(2, "dirichlet"), (4, "msd"), (4, "dirichlet"), (4, "l0")])
 def test_mass_energy_parity(nd, shape, order, bc):
     from paper_1203_1263_amd.nlse import Grid
     from gpu_util import to_dev, pot_dev
