@@ -139,6 +139,23 @@ int nlse_set_potential(nlse_grid *g, const void *V_dev);
  * NLSE_EUNSTABLE from nlse_mass_energy). */
 int nlse_step_rk4(nlse_grid *g, int order, int bc, double dt, int64_t nsteps);
 
+/* Frames (Sec. "Chunk-size Limitations": the integrator hands the field back
+ * to the host every `chunk` steps).  Runs nframes chunks of `chunk` RK4 steps
+ * (as nlse_step_rk4) and copies the field after chunk j into
+ * frames_host + j * npts elements (interleaved complex of the grid's element
+ * type; for NLSE_COMPENSATED grids the stored FP32 field).  The copies
+ * overlap the integration: after each chunk Psi is copied device to device,
+ * on the grid's stream, into one half of stage_dev (caller-owned device
+ * memory, 16-byte aligned, stage_bytes >= 2 * npts * element bytes), and a
+ * library-owned stream moves that half to the host while the next chunk
+ * runs (the calling thread orders the two streams, waiting on events).  frames_host (caller-owned, nframes * npts elements) should be
+ * pinned (hipHostMalloc) for the overlap; pageable memory gives the same
+ * frames, copied without overlap.  Synchronises: returns after the last
+ * frame is on the host.  chunk >= 1, nframes >= 0 (0: no work). */
+int nlse_run_frames(nlse_grid *g, int order, int bc, double dt, int64_t chunk,
+                    int64_t nframes, void *frames_host, void *stage_dev,
+                    size_t stage_bytes);
+
 /* Mass M = h^d sum |Psi|^2 and energy
  *   E = h^d [ sum_interior -a Re(conj(Psi) L Psi) + sum ( V|Psi|^2 - (s/2)|Psi|^4 ) ]
  * (the standard NLSE invariants; the paper defines neither), with L the

@@ -146,6 +146,8 @@ struct nlse_grid {
   int tile[2][3];  // [0] CD2, [1] 2SHOC
   hipStream_t cap = nullptr;  // private stream used only for graph capture
   std::map<GraphKey, hipGraphExec_t> graphs;
+  hipStream_t copy = nullptr;  // frames: device-to-host copies
+  hipEvent_t snap[2] = {nullptr, nullptr}, copied[2] = {nullptr, nullptr};
 };
 
 static void drop_graphs(nlse_grid* g) {
@@ -201,14 +203,16 @@ static void default_tile(const Shape& s, int dtype, unsigned flags, int order, i
     t[0] = 64; t[1] = 4; t[2] = 1;
   } else {
     t[0] = 32; t[1] = 8;
-    // z-chunks: aim for enough workgroups to fill 256 CUs several times over
-    int64_t xy = ((s.n[0] + 31) / 32) * ((s.n[1] + 7) / 8);
-    int64_t nzi = s.n[2] - 2;
-    int64_t want = 4096;
-    int64_t nch = (want + xy - 1) / xy;
-    if (nch < 1) nch = 1;
-    int64_t cz = (nzi + nch - 1) / nch;
-    if (cz < 8) cz = 8;
+    // z-chunk: each workgroup marches its planes one after another, so small
+    // grids need short chunks (enough workgroups to hide the per-plane load
+    // latency) and large ones long chunks (fewer re-read halo planes).
+    // Aim at ~1024 workgroups with 1 <= cz <= 16 (measured best from 10^3 to
+    // 256^3 points).
+    const int64_t xy = ((s.n[0] + 31) / 32) * ((s.n[1] + 7) / 8);
+    const int64_t nzi = s.n[2] - 2;
+    int64_t cz = (nzi * xy + 1023) / 1024;
+    if (cz < 1) cz = 1;
+    if (cz > 16) cz = 16;
     // the fused kernels fill a 7-plane pipeline per chunk: longer chunks
     if (fused_eligible(s, dtype, flags, order)) cz = 32;
     if (cz > nzi) cz = nzi;
@@ -267,6 +271,11 @@ extern "C" int nlse_destroy_grid(nlse_grid* g) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
   drop_graphs(g);
   if (g->cap) (void)hipStreamDestroy(g->cap);
+  if (g->copy) (void)hipStreamDestroy(g->copy);
+  for (int k = 0; k < 2; ++k) {
+    if (g->snap[k]) (void)hipEventDestroy(g->snap[k]);
+    if (g->copied[k]) (void)hipEventDestroy(g->copied[k]);
+  }
   delete g;
   return NLSE_OK;
 }
@@ -426,6 +435,61 @@ extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t
   return NLSE_OK;
 }
 
+// Frames: after each chunk, Psi is snapshotted on the grid's stream into one
+// half of the staging buffer (a copy kernel), and the copy stream moves that
+// snapshot to the host while the next chunk integrates.  The host orders the
+// two streams itself: it enqueues chunk j+1 first, then waits for snapshot j
+// and only then enqueues copy j, which has no stream dependency.  (A
+// device-to-host copy made to wait on the other stream's event did not
+// overlap the kernels: frames then cost the full copy time.)  A half is
+// refilled only after the host has seen the copy that last read it finish.
+extern "C" int nlse_run_frames(nlse_grid* g, int order, int bc, double dt, int64_t chunk, int64_t nframes,
+                               void* frames_host, void* stage_dev, size_t stage_bytes) {
+  if (!g) return fail(NLSE_EINVAL, "g is NULL");
+  int rc = check_scheme(order, bc);
+  if (rc) return rc;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
+  if (chunk < 1) return fail(NLSE_EINVAL, "chunk must be >= 1");
+  if (nframes < 0) return fail(NLSE_EINVAL, "nframes must be >= 0");
+  if (nframes == 0) return NLSE_OK;
+  const size_t fb = (size_t)g->shape.npts * (g->dtype == NLSE_F32 ? 8 : 16);
+  if (!frames_host) return fail(NLSE_EINVAL, "frames_host is NULL");
+  if (!stage_dev) return fail(NLSE_EINVAL, "stage_dev is NULL");
+  if ((uintptr_t)stage_dev % 16) return fail(NLSE_EINVAL, "stage_dev must be 16-byte aligned");
+  if (stage_bytes < 2 * fb) return fail(NLSE_ENOMEM, "stage_bytes %zu < 2 * %zu", stage_bytes, fb);
+  hipError_t e = hipSuccess;
+  if (!g->copy) e = hipStreamCreateWithFlags(&g->copy, hipStreamNonBlocking);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    if (!g->snap[k]) e = hipEventCreateWithFlags(&g->snap[k], hipEventDisableTiming);
+    if (e == hipSuccess && !g->copied[k]) e = hipEventCreateWithFlags(&g->copied[k], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) return hip_fail(e, "creating the copy stream / events");
+  char* stage = static_cast<char*>(stage_dev);
+  char* host = static_cast<char*>(frames_host);
+  // frame j: wait until its snapshot is complete, then copy it out
+  auto copy_out = [&](int64_t j) -> hipError_t {
+    const int k = (int)(j & 1);
+    hipError_t r = hipEventSynchronize(g->snap[k]);
+    if (r == hipSuccess) r = hipMemcpyAsync(host + j * fb, stage + k * fb, fb, hipMemcpyDeviceToHost, g->copy);
+    if (r == hipSuccess) r = hipEventRecord(g->copied[k], g->copy);
+    return r;
+  };
+  for (int64_t j = 0; j < nframes; ++j) {
+    const int k = (int)(j & 1);
+    rc = nlse_step_rk4(g, order, bc, dt, chunk);
+    if (rc) return rc;
+    if (j >= 2) e = hipEventSynchronize(g->copied[k]);  // frame j-2 has left half k
+    if (e == hipSuccess) e = nlse_launch_copy(stage + k * fb, g->psi, (int64_t)fb, g->stream);
+    if (e == hipSuccess) e = hipEventRecord(g->snap[k], g->stream);
+    if (e == hipSuccess && j >= 1) e = copy_out(j - 1);
+    if (e != hipSuccess) return hip_fail(e, "frame copy");
+  }
+  e = copy_out(nframes - 1);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->copy);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+  return e == hipSuccess ? NLSE_OK : hip_fail(e, "frame synchronisation");
+}
+
 extern "C" int nlse_mass_energy(nlse_grid* g, int order, int bc, double* mass, double* energy) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
   int rc = check_scheme(order, bc);
@@ -537,7 +601,7 @@ static std::vector<std::array<int, 3>> candidates(const nlse_grid* g, int order)
   } else {
     const int64_t nzi = s.n[2] - 2;
     for (auto xy : {std::array<int, 2>{32, 8}, {64, 4}, {64, 8}})
-      for (int cz : {8, 16, 32, 64}) {
+      for (int cz : {1, 2, 4, 8, 16, 32, 64}) {
         std::array<int, 3> t = {xy[0], xy[1], (int)std::min<int64_t>(cz, nzi)};
         bool dup = false;
         for (auto& o : out) dup |= (o == t);

@@ -56,4 +56,5 @@ hipError_t nlse_launch_fused3d_pair0(const nlse::StageLaunch& L, const void* psi
                                      hipStream_t st);
 hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st);
 hipError_t nlse_launch_fill_zero(void* p, int64_t nbytes, hipStream_t st);
+hipError_t nlse_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t st);
 extern "C" int nlse_internal_tile_supported(int ndim, int dtype, const int tile[3]);

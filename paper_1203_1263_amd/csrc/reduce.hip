@@ -180,6 +180,12 @@ __global__ void fill_zero_kernel(uint32_t* p, int64_t nwords) {
   for (; i < nwords; i += stride) p[i] = 0u;
 }
 
+__global__ void copy_words_kernel(const uint2* __restrict__ src, uint2* __restrict__ dst, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
 template <typename T>
 static hipError_t reduce_typed(const ReduceLaunch& R, hipStream_t st) {
   View<T> g;
@@ -209,6 +215,19 @@ static hipError_t reduce_typed(const ReduceLaunch& R, hipStream_t st) {
 
 hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st) {
   return R.dtype == 0 ? nlse::reduce_typed<float>(R, st) : nlse::reduce_typed<double>(R, st);
+}
+
+// Device-to-device copy of nbytes (a multiple of 8, both pointers 8-byte
+// aligned) as a kernel: it runs at HBM speed on the given stream, where a
+// runtime copy may go to a copy engine of far lower bandwidth.
+hipError_t nlse_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t st) {
+  int64_t n = nbytes / 8;
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(nlse::copy_words_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                     static_cast<const uint2*>(src), static_cast<uint2*>(dst), n);
+  return hipGetLastError();
 }
 
 // Clears nbytes (a multiple of 4) with a kernel instead of a memset node, so

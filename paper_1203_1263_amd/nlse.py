@@ -74,6 +74,8 @@ def load_library() -> ctypes.CDLL:
         "nlse_set_potential": (ctypes.c_int, [vp, vp]),
         "nlse_step_rk4": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64]),
         "nlse_mass_energy": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, dp]),
+        "nlse_run_frames": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
+                                           ctypes.c_int64, vp, vp, ctypes.c_size_t]),
         "nlse_get_state": (ctypes.c_int, [vp, vp]),
         "nlse_set_state": (ctypes.c_int, [vp, vp]),
         "nlse_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
@@ -155,6 +157,12 @@ def nlse_set_potential(g, V_ptr):
 
 def nlse_step_rk4(g, order: int, bc: int, dt: float, nsteps: int):
     _check(load_library().nlse_step_rk4(g, order, bc, dt, nsteps), "nlse_step_rk4")
+
+
+def nlse_run_frames(g, order: int, bc: int, dt: float, chunk: int, nframes: int, frames_host_ptr,
+                    stage_ptr, stage_bytes: int):
+    _check(load_library().nlse_run_frames(g, order, bc, dt, chunk, nframes, frames_host_ptr, stage_ptr,
+                                          stage_bytes), "nlse_run_frames")
 
 
 def nlse_mass_energy(g, order: int, bc: int) -> Tuple[float, float]:
@@ -353,6 +361,24 @@ class Grid:
 
     def step(self, dt: float, nsteps: int, order: int = NLSE_2SHOC, bc="msd"):
         nlse_step_rk4(self._g, order, BC[bc] if isinstance(bc, str) else bc, dt, nsteps)
+
+    def run_frames(self, dt: float, chunk: int, nframes: int, order: int = NLSE_2SHOC, bc="msd",
+                   out=None, pinned: bool = True):
+        """Advance nframes * chunk steps; returns the field after every chunk
+        as a host tensor of shape (nframes, *psi.shape) (pinned unless
+        ``pinned=False`` or ``out`` is given)."""
+        import torch
+        if out is None:
+            out = torch.empty((nframes,) + tuple(self.psi.shape), dtype=self.psi.dtype, pin_memory=pinned)
+        if out.is_cuda or not out.is_contiguous() or out.dtype != self.psi.dtype or \
+                out.numel() < nframes * self.psi.numel():
+            raise ValueError("out must be a contiguous host tensor of nframes fields")
+        if getattr(self, "_stage", None) is None:
+            self._stage = torch.empty(2 * self.psi.numel(), dtype=self.psi.dtype, device=self.psi.device)
+        nlse_run_frames(self._g, order, BC[bc] if isinstance(bc, str) else bc, dt, chunk, nframes,
+                        out.data_ptr() if nframes else None, self._stage.data_ptr(),
+                        self._stage.numel() * self._stage.element_size())
+        return out
 
     def mass_energy(self, order: int = NLSE_CD2, bc="dirichlet"):
         return nlse_mass_energy(self._g, order, BC[bc] if isinstance(bc, str) else bc)

@@ -94,6 +94,7 @@ def test_create_grid_validates_before_launch(bad, code):
 
 def test_null_grid_is_rejected(lib):
     assert lib.nlse_step_rk4(None, 2, 0, 0.1, 1) == nlse.NLSE_EINVAL
+    assert lib.nlse_run_frames(None, 2, 0, 0.1, 1, 1, None, None, 0) == nlse.NLSE_EINVAL
     assert lib.nlse_destroy_grid(None) == nlse.NLSE_EINVAL
     assert lib.nlse_set_potential(None, None) == nlse.NLSE_EINVAL
 

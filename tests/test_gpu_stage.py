@@ -167,6 +167,46 @@ def test_graph_replay_equals_direct_launches(shape, dtype, order, bc, comp, fuse
     assert rel_l2(runs[0][2].astype(np.complex128), ref) < TOL[dtype]
 
 
+FRAME_CASES = [((37, 150), "f32", True, 7, True), ((37, 150), "f32", False, 1, False),
+               ((11, 9, 70), "f64", False, 3, True), ((600,), "f32", True, 2, True)]
+
+
+@pytest.mark.parametrize("shape,dtype,comp,chunk,pinned", FRAME_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-{c[1]}-c{int(c[2])}-chunk{c[3]}-pin{int(c[4])}"
+                              for c in FRAME_CASES])
+def test_frames_equal_stepwise_fields(shape, dtype, comp, chunk, pinned):
+    """nlse_run_frames delivers, after every chunk, the field that the same
+    number of nlse_step_rk4 steps produces (bitwise), with pinned and pageable
+    host buffers and with more frames than staging halves; the field left on
+    the device is the last frame."""
+    import torch
+    from paper_1203_1263_amd import nlse
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem(shape, 90 + chunk)
+    dt = 0.5 * oracle.dt_max(len(shape), 4, h, a)
+    nframes = 5
+    psi = to_dev(u, dtype)
+    g = Grid(psi, h, a, s, V=pot_dev(V, dtype), compensated=comp)
+    frames = g.run_frames(dt, chunk, nframes, order=4, bc="msd", pinned=pinned)
+    assert frames.is_pinned() == pinned
+    assert torch.equal(frames[-1], psi.cpu())
+    with pytest.raises(nlse.NLSEError) as e:  # staging smaller than two fields
+        nlse.nlse_run_frames(g._g, 4, 1, dt, chunk, 1, frames.data_ptr(), g._stage.data_ptr(),
+                             g._stage.numel() * g._stage.element_size() - 8)
+    assert e.value.code == nlse.NLSE_ENOMEM
+    g.close()
+    psi2 = to_dev(u, dtype)
+    g2 = Grid(psi2, h, a, s, V=pot_dev(V, dtype), compensated=comp)
+    for j in range(nframes):
+        g2.step(dt, chunk, order=4, bc="msd")
+        torch.cuda.synchronize()
+        assert torch.equal(frames[j], psi2.cpu()), j
+    g2.close()
+    ref = oracle.rk4(u, h, a, s, dt, chunk, V=V, order=4, bc="msd")
+    assert rel_l2(frames[0].numpy().astype(np.complex128), ref) < TOL[dtype]
+
+
 def test_run_twice_bitwise():
     u, V, h, a, s = smooth_problem((17, 23, 91), 3)
     dt = 0.5 * oracle.dt_max(3, 4, h, a)
