@@ -176,7 +176,9 @@ int nlse_set_state(nlse_grid *g, const void *lo_dev);
 
 /* Tile shape used by the stage kernels: (tx, ty, cz) = x-width, y-height and
  * z-chunk length (unused entries 1).  Any supported shape gives bitwise
- * identical results.  nlse_autotune times the candidates for
+ * identical results.  1D: 256 runs each stage as a kernel; 1024 (the
+ * default for grids of at most 1024 FP64 / 2048 FP32 points) runs every
+ * step of a call in one on-chip workgroup.  nlse_autotune times the candidates for
  * (order, bc) on this grid (running stage kernels on scratch copies, the
  * field is not changed; for fused 3D grids only the z-chunk of the 32x8
  * tile is tuned), keeps the fastest and stores it in the cache file

@@ -32,7 +32,7 @@ COMMON = [
     "-I", INCLUDE, "-I", CSRC,
 ]
 
-SOURCES = ["stage3d.hip", "stage3d_fused.hip", "stage2d.hip", "stage1d.hip", "stage.hip", "batch.hip", "surrogate.hip", "reduce.hip",
+SOURCES = ["stage3d.hip", "stage3d_fused.hip", "stage1d_resident.hip", "stage2d.hip", "stage1d.hip", "stage.hip", "batch.hip", "surrogate.hip", "reduce.hip",
            "api.cpp", "api_batch.cpp", "api_surrogate.cpp"]
 
 

@@ -198,7 +198,10 @@ static bool fused_eligible(const Shape& s, int dtype, unsigned flags, int order)
 
 static void default_tile(const Shape& s, int dtype, unsigned flags, int order, int t[3]) {
   if (s.ndim == 1) {
-    t[0] = 256; t[1] = 1; t[2] = 1;
+    // grids that fit on chip run every step in one workgroup (tile 1024)
+    t[0] = s.npts <= nlse_resident1d_max_points(dtype) ? 1024 : 256;
+    t[1] = 1;
+    t[2] = 1;
   } else if (s.ndim == 2) {
     t[0] = 64; t[1] = 4; t[2] = 1;
   } else {
@@ -347,6 +350,12 @@ static hipError_t enqueue_step(const nlse_grid* g, int order, int bc, double dt,
 // Enqueue nsteps RK4 steps on stream st (no host synchronisation).
 static hipError_t enqueue_steps(const nlse_grid* g, int order, int bc, double dt, const int tile[3], int64_t nsteps,
                                 hipStream_t st) {
+  if (g->shape.ndim == 1 && tile[0] == 1024) {
+    nlse::StageLaunch L = grid_launch(g, order, bc, tile);
+    L.psi = g->psi;
+    L.lo = L.comp ? g->work + g->lay.lo : nullptr;
+    return nlse_launch_resident1d(L, nsteps, dt, st);
+  }
   int64_t left = nsteps;
   if (bc != NLSE_BC_L0 && fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 && tile[1] == 8) {
     // Pairs of steps Psi -> workspace -> Psi (the fused launches cannot
@@ -565,6 +574,7 @@ static size_t lds_bytes_3d(int order, int dtype, int tx, int ty) {
 
 static bool tile_fits(const nlse_grid* g, int order, const int t[3]) {
   if (!nlse_internal_tile_supported(g->shape.ndim, g->dtype, t)) return false;
+  if (g->shape.ndim == 1 && t[0] == 1024 && g->shape.npts > nlse_resident1d_max_points(g->dtype)) return false;
   if (g->shape.ndim == 3) {
     if (t[2] > g->shape.n[2] - 2) return false;
     // keep each workgroup within 64 KiB of LDS so several fit on a CU
@@ -587,7 +597,9 @@ static std::vector<std::array<int, 3>> candidates(const nlse_grid* g, int order)
   std::vector<std::array<int, 3>> out;
   const Shape& s = g->shape;
   if (s.ndim == 1) {
-    out.push_back({256, 1, 1});
+    // the whole-grid kernel replaces four launches per step by none: when
+    // it fits it is the only candidate (its runs would change the field)
+    out.push_back({s.npts <= nlse_resident1d_max_points(g->dtype) ? 1024 : 256, 1, 1});
   } else if (s.ndim == 2) {
     for (auto t : {std::array<int, 3>{32, 8, 1}, {64, 4, 1}, {64, 8, 1}}) out.push_back(t);
   } else if (fused_eligible(s, g->dtype, g->flags, order)) {

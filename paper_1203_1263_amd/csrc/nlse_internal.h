@@ -55,6 +55,11 @@ hipError_t nlse_launch_fused3d(const nlse::StageLaunch& L, const void* psi_in, v
 hipError_t nlse_launch_fused3d_pair0(const nlse::StageLaunch& L, const void* psi, void* acc, void* mid, double dt,
                                      hipStream_t st);
 hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st);
+// Whole-grid 1D integrator (one workgroup, grid on chip): nsteps RK4 steps of
+// size dt in one launch, updating L.psi (and L.lo) in place; bitwise equal
+// to the per-stage kernels.  Grids of 3 .. nlse_resident1d_max_points(dtype).
+hipError_t nlse_launch_resident1d(const nlse::StageLaunch& L, int64_t nsteps, double dt, hipStream_t st);
+int64_t nlse_resident1d_max_points(int dtype);
 hipError_t nlse_launch_fill_zero(void* p, int64_t nbytes, hipStream_t st);
 hipError_t nlse_launch_copy(void* dst, const void* src, int64_t nbytes, hipStream_t st);
 extern "C" int nlse_internal_tile_supported(int ndim, int dtype, const int tile[3]);

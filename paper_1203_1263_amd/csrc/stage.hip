@@ -20,7 +20,8 @@ hipError_t nlse_launch_stage(const nlse::StageLaunch& L, hipStream_t st) {
 extern "C" int nlse_internal_tile_supported(int ndim, int dtype, const int tile[3]) {
   (void)dtype;
   const int tx = tile[0], ty = tile[1], cz = tile[2];
-  if (ndim == 1) return tx == 256 && ty == 1 && cz == 1;
+  // 1D: 256 = per-stage kernels, 1024 = whole-grid kernel (small grids)
+  if (ndim == 1) return (tx == 256 || tx == 1024) && ty == 1 && cz == 1;
   const bool xy = (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 64 && ty == 8);
   if (ndim == 2) return xy && cz == 1;
   return xy && cz >= 1 && cz <= 4096;

@@ -124,6 +124,43 @@ def test_fused_pairs_equal_four_passes(shape, bc, comp, withV, cz):
     assert rel_l2(fused, ref) < TOL["f32"]
 
 
+RES_CASES = [(n, dt, o, bc, c) for (n, dt) in ((3, "f64"), (600, "f64"), (1024, "f64"), (1030, "f32"), (2048, "f32"))
+             for o, bc in ((2, "dirichlet"), (4, "msd"), (4, "l0"), (2, "msd")) for c in ((False, True) if dt == "f32" else (False,))]
+
+
+@pytest.mark.parametrize("n,dtype,order,bc,comp", RES_CASES,
+                         ids=[f"{c[0]}-{c[1]}-o{c[2]}-{c[3]}-c{int(c[4])}" for c in RES_CASES])
+def test_resident_1d_equals_per_stage_kernels(n, dtype, order, bc, comp):
+    """1D grids up to 1024 (FP64) / 2048 (FP32) points run all their steps
+    in one workgroup (tile 1024, the default there); the per-stage kernels
+    (tile 256) must give the same bits, and both must match the oracle."""
+    u, V, h, a, s = smooth_problem((n,), 70 + n % 13)
+    dt = 0.5 * oracle.dt_max(1, order, h, a)
+    res = run_gpu(u, h, a, s, dt, 37, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=(1024, 1, 1))
+    per = run_gpu(u, h, a, s, dt, 37, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=(256, 1, 1))
+    assert np.array_equal(res, per)
+    ref = oracle.rk4(u, h, a, s, dt, 37, V=V, order=order, bc=bc)
+    assert rel_l2(res, ref) < TOL[dtype]
+
+
+def test_resident_1d_limits():
+    """The whole-grid tile is the default only where it fits, and asking for
+    it on a larger grid is refused."""
+    import torch
+    from paper_1203_1263_amd import nlse
+    from paper_1203_1263_amd.nlse import Grid
+    for n, dtype, want in ((1024, torch.complex128, 1024), (1025, torch.complex128, 256),
+                           (2048, torch.complex64, 1024), (2049, torch.complex64, 256)):
+        psi = torch.ones(n, dtype=dtype, device="cuda")
+        g = Grid(psi, 0.1, 1.0, 1.0)
+        assert g.tile(4)[0] == want and g.tile(2)[0] == want
+        if want == 256:
+            with pytest.raises(nlse.NLSEError) as e:
+                g.set_tile(4, (1024, 1, 1))
+            assert e.value.code == nlse.NLSE_EUNSUPPORTED
+        g.close()
+
+
 GRAPH_CASES = [((600,), "f32", 2, "dirichlet", False, False), ((37, 150), "f32", 4, "msd", True, False),
                ((37, 150), "f64", 4, "dirichlet", False, False), ((11, 9, 70), "f32", 4, "msd", True, False),
                ((11, 9, 70), "f32", 4, "msd", True, True), ((11, 9, 70), "f64", 2, "msd", False, False)]
