@@ -16,7 +16,13 @@ problems"; the shapes below follow those examples and the benchmark configs):
   uses as its approximate profile), 1024^2, h=0.25, s=-1.
 * ``ring3d``     -- Thomas-Fermi background in a harmonic trap
   V = 0.5 sum w_d x_d^2 with an embedded vortex ring (after Eq. 3dvr1, with a
-  tanh core instead of the numerically exact profile), 256^3 and 87x87x203.
+  tanh core, or with ``core="exact"`` the numerically exact vortex profile),
+  256^3 and 87x87x203.
+* ``ring3d_paper`` -- the paper's own 3D example (Eq. 3dvr1): the exact
+  charge-1 vortex profile in the ring's cross-section on a unit background,
+  V = 0, with the co-moving back-flow phase e^{i c z / (2a)}.
+* ``vortex_profile`` -- the numerically exact radial profile of a dark
+  vortex (Eq. exmp2Dvort), found by Newton's method.
 * ``batch2d``    -- 512 independent 2D problems of uneven size with Gaussian
   random-field initial conditions and smooth random potentials.
 * ``surrogate2d`` -- 256^2 fields with 2-8 random vortices.
@@ -106,34 +112,91 @@ def _vortex_centres(g: np.random.Generator, nv: int, box: float, min_dist: float
     return np.array(pts)
 
 
-def vortex_field(x: np.ndarray, y: np.ndarray, centres, charges) -> np.ndarray:
+# ------------------------------------------------------------------ exact vortex profile
+
+def vortex_profile(m: int = 1, a: float = 1.0, rmax: float = 40.0, dr: float = 0.01, tol: float = 1e-11,
+                   max_iter: int = 30):
+    """Radial profile g of the stationary charge-m dark vortex on a unit
+    background (Eq. exmp2Dvort with s = -1, V = 0, so Omega = -1):
+
+        a (g'' + g'/r - m^2 g / r^2) + (1 - g^2) g = 0,   g(0) = 0,
+
+    with g(rmax) = 1 - a m^2 / (2 rmax^2) (the far-field expansion).  At
+    background density rho the profile is sqrt(rho) g(r sqrt(rho)).  Solved
+    by Newton's method on a second-order finite-difference grid with a
+    banded Jacobian (the paper finds the numerically exact profile with a
+    Newton-Krylov solver).  Returns (r, g) on r = 0, dr, ..., rmax."""
+    from scipy.linalg import solve_banded
+    M = int(round(rmax / dr))
+    r = np.arange(M + 1) * dr
+    rj = r[1:M]
+    gM = 1.0 - a * m * m / (2.0 * rmax * rmax)
+    g = np.tanh(r / math.sqrt(2.0 * a)) ** abs(m)
+    g[0], g[M] = 0.0, gM
+    lo_c = a * (1.0 / dr ** 2 - 1.0 / (2.0 * rj * dr))
+    up_c = a * (1.0 / dr ** 2 + 1.0 / (2.0 * rj * dr))
+    for _ in range(max_iter):
+        gj, gm, gp = g[1:M], g[0:M - 1], g[2:M + 1]
+        F = lo_c * gm + up_c * gp + a * (-2.0 / dr ** 2 - m * m / rj ** 2) * gj + (1.0 - gj * gj) * gj
+        ab = np.zeros((3, M - 1))
+        ab[0, 1:] = up_c[:-1]
+        ab[1, :] = a * (-2.0 / dr ** 2 - m * m / rj ** 2) + 1.0 - 3.0 * gj * gj
+        ab[2, :-1] = lo_c[1:]
+        delta = solve_banded((1, 1), ab, -F)
+        g[1:M] += delta
+        step = np.max(np.abs(delta))
+        if step < tol:
+            break
+    if step > 1e-8:  # rounding keeps fine grids from reaching tol; a real failure is far above this
+        raise RuntimeError("vortex profile: Newton did not converge")
+    return r, g
+
+
+def _core(rr: np.ndarray, profile, a: float, m: int = 1) -> np.ndarray:
+    """Profile value at radii rr: interpolated inside the table, far-field
+    expansion 1 - a m^2/(2 r^2) beyond it."""
+    r, g = profile
+    out = np.interp(rr, r, g)
+    far = rr > r[-1]
+    if np.any(far):
+        out[far] = 1.0 - a * m * m / (2.0 * rr[far] ** 2)
+    return out
+
+
+def vortex_field(x: np.ndarray, y: np.ndarray, centres, charges, profile=None, a: float = 1.0) -> np.ndarray:
+    """Product of charge-m_j vortices: tanh(r_j) cores, or with ``profile``
+    (from :func:`vortex_profile`, same a) the exact cores."""
     X, Y = np.meshgrid(x, y, indexing="xy")  # shape (Ny, Nx), x fastest
     psi = np.ones_like(X, dtype=np.complex128)
     for (cx, cy), m in zip(centres, charges):
         dx, dy = X - cx, Y - cy
         r = np.hypot(dx, dy)
-        psi *= np.tanh(r) * np.exp(1j * m * np.arctan2(dy, dx))
+        core = np.tanh(r) if profile is None else _core(r, profile, a, abs(int(m)))
+        psi *= core * np.exp(1j * m * np.arctan2(dy, dx))
     return psi
 
 
 def vortex2d(n: int = 1024, h: float = 0.25, nv: int = 4, nsteps: int = 2000,
-             index: int = 1, box: float = 64.0, min_dist: float = 8.0) -> Problem:
+             index: int = 1, box: float = 64.0, min_dist: float = 8.0, core: str = "tanh") -> Problem:
     g = rng(index)
     centres = _vortex_centres(g, nv, min(box, 0.4 * n * h), min_dist)
     charges = g.choice([-1, 1], size=nv)
     x = axis(n, h)
-    psi = vortex_field(x, x, centres, charges)
+    profile = vortex_profile(1, 1.0) if core == "exact" else None
+    psi = vortex_field(x, x, centres, charges, profile=profile, a=1.0)
     return Problem("vortex2d", psi, h, 1.0, -1.0, None, 4, "msd", nsteps,
-                   meta={"centres": centres, "charges": charges})
+                   meta={"centres": centres, "charges": charges, "core": core})
 
 
 # ------------------------------------------------------------------ 3D ring
 
 def ring3d(shape=(256, 256, 256), h: float = 0.1, nsteps: int = 1000, index: int = 2,
-           a: float = 0.5, s: float = -1.0) -> Problem:
+           a: float = 0.5, s: float = -1.0, core: str = "tanh") -> Problem:
     """shape = (Nz, Ny, Nx).  Thomas-Fermi density rho = mu - V (mu = max V + 1)
     with a vortex ring of radius R around the z axis: u = (r_perp - R) + i z,
-    psi = sqrt(rho) tanh(|u|/xi) u/|u|, xi = sqrt(a/mu)."""
+    psi = sqrt(rho) tanh(|u|/xi) u/|u|, xi = sqrt(a/mu); with core="exact"
+    the tanh is replaced by the exact profile at density mu,
+    g(|u| sqrt(mu)) (see :func:`vortex_profile`)."""
     g = rng(index)
     nz, ny, nx = shape
     w = g.uniform(0.01, 0.1, size=3)
@@ -150,9 +213,43 @@ def ring3d(shape=(256, 256, 256), h: float = 0.1, nsteps: int = 1000, index: int
     au = np.abs(u)
     with np.errstate(invalid="ignore", divide="ignore"):
         ph = np.where(au > 0, u / np.where(au > 0, au, 1.0), 0.0)
-    psi = np.sqrt(rho) * np.tanh(au / xi) * ph
+    if core == "exact":
+        prof = vortex_profile(1, a)
+        cz = _core((au * math.sqrt(mu)).ravel(), prof, a).reshape(au.shape)
+    else:
+        cz = np.tanh(au / xi)
+    psi = np.sqrt(rho) * cz * ph
     return Problem("ring3d", psi.astype(np.complex128), h, a, s, V, 4, "msd", nsteps,
-                   meta={"w": w, "R": R, "mu": mu})
+                   meta={"w": w, "R": R, "mu": mu, "core": core})
+
+
+def ring_velocity(d: float, a: float) -> float:
+    """Asymptotic speed of a large vortex ring of radius d on a unit
+    background of iPsi_t = -a Lap Psi + |Psi|^2 Psi: the classical
+    (ln(8R/xi) - 0.615)/(2R) law of the defocusing NLSE in units with
+    a = 1/2, carried to general a by x -> x sqrt(2a)."""
+    return (a / d) * (math.log(8.0 * d / math.sqrt(2.0 * a)) - 0.615)
+
+
+def ring3d_paper(shape=(64, 64, 64), h: float = 0.5, d: float = 5.0, a: float = 1.0,
+                 nsteps: int = 1000) -> Problem:
+    """The paper's 3D example (Eq. 3dvr1): psi = g(r, z) e^{i c z / (2a)},
+    g the exact charge-1 vortex at (r = d, z = 0) of the r-z half-plane on a
+    unit background, V = 0, s = -1, c the ring's asymptotic speed
+    (:func:`ring_velocity`), MSD boundaries, 2SHOC."""
+    nz, ny, nx = shape
+    x, y, z = axis(nx, h), axis(ny, h), axis(nz, h)
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    u = (np.hypot(X, Y) - d) + 1j * Z
+    au = np.abs(u)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ph = np.where(au > 0, u / np.where(au > 0, au, 1.0), 0.0)
+    prof = vortex_profile(1, a)
+    g = _core(au.ravel(), prof, a).reshape(au.shape) * ph
+    c = ring_velocity(d, a)
+    psi = g * np.exp(1j * (c / (2.0 * a)) * Z)
+    return Problem("ring3d_paper", psi.astype(np.complex128), h, a, -1.0, None, 4, "msd", nsteps,
+                   meta={"d": d, "c": c})
 
 
 # ------------------------------------------------------------------ batch

@@ -244,6 +244,22 @@ def test_frames_equal_stepwise_fields(shape, dtype, comp, chunk, pinned):
     assert rel_l2(frames[0].numpy().astype(np.complex128), ref) < TOL[dtype]
 
 
+@pytest.mark.parametrize("which,dtype,comp", [("paper", "f32", True), ("paper", "f64", False),
+                                               ("trap_exact", "f32", True)])
+def test_exact_profile_ring_inputs(which, dtype, comp):
+    """The paper's own 3D example (exact vortex core on a unit background
+    with the back-flow phase, Eq. 3dvr1) and the trapped ring with the exact
+    core, 60 steps, against the oracle."""
+    if which == "paper":
+        p = wl.ring3d_paper(shape=(30, 34, 36), h=0.5, d=4.0)
+    else:
+        p = wl.ring3d(shape=(30, 34, 36), h=0.3, core="exact")
+    dt = 0.5 * oracle.dt_max(3, 4, p.h, p.a)
+    out = run_gpu(p.psi0, p.h, p.a, p.s, dt, 60, V=p.V, order=4, bc="msd", dtype=dtype, compensated=comp)
+    ref = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, 60, V=p.V, order=4, bc="msd")
+    assert rel_l2(out, ref) < TOL[dtype]
+
+
 def test_run_twice_bitwise():
     u, V, h, a, s = smooth_problem((17, 23, 91), 3)
     dt = 0.5 * oracle.dt_max(3, 4, h, a)
