@@ -72,8 +72,8 @@ BatchLayout layout(int nsims, int dtype, unsigned flags, int64_t tot, int64_t ni
   L.bufB = off; off += field;
   L.lo = off; if (flags & NLSE_COMPENSATED) off += field;
   L.items = off; off += a256(sizeof(nlse::BatchItem) * (size_t)nitems);
-  L.chunks = off; off += a256(sizeof(int) * (size_t)(kMaxChunks + 1));
-  L.barrier = off; off += 256;
+  L.chunks = off; off += a256(sizeof(int) * (size_t)(5 * kMaxChunks + 1));
+  L.barrier = off; off += a256(sizeof(unsigned) * (size_t)(kMaxChunks + 2));
   L.zero = off; off += 256;
   L.partials = off; off += a256((size_t)max_blocks * 3 * sizeof(double));
   L.out = off; off += a256((size_t)nsims * 3 * sizeof(double));
@@ -88,7 +88,7 @@ struct nlse_batch {
   unsigned flags;
   std::vector<nlse_sim_desc> desc;
   int64_t total_pts, nitems;
-  int nchunks;
+  int nchunks, ngroups;
   void* psi;
   const void* vpool;
   char* work;
@@ -109,8 +109,8 @@ extern "C" int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc* sims, 
 }
 
 static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
-  // reset the arrival counter; the error flag next to it stays sticky
-  hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier, 4, st);
+  // reset the group arrival counters; the error flag before them stays sticky
+  hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier + 8, 4 * (int64_t)b->ngroups, st);
   if (e != hipSuccess) return e;
   nlse::BatchLaunch L;
   L.dtype = b->dtype;
@@ -165,9 +165,8 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   if (e == hipSuccess) e = nlse_batch_occupancy(dtype, (flags & NLSE_COMPENSATED) ? 1 : 0, &occ);
   if (e != hipSuccess) return nlse_hip_fail(e, "querying occupancy");
   if (occ < 1 || cus < 1) return nlse_fail(NLSE_EDEVICE, "the batched kernel does not fit on a CU");
-  // Each grid barrier costs one L2 write-back and invalidate per workgroup,
-  // serialised per XCD, while the item pipeline already keeps the memory
-  // system busy with three workgroups per CU: cap there.
+  // The item pipeline keeps the memory system busy with three workgroups
+  // per CU; more only add barrier arrivals (measured best: 3).
   occ = std::min(occ, kMaxWgPerCu);
   int64_t nchunks = std::min<int64_t>({(int64_t)occ * cus, items, (int64_t)kMaxChunks});
 
@@ -188,9 +187,8 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   B->cap = nullptr;
 
   // device descriptors: the same double constants the single-grid path uses
-  std::vector<nlse::BatchItem> it;
-  std::vector<double> cost;
-  it.reserve((size_t)items);
+  std::vector<std::vector<nlse::BatchItem>> tiles(nsims);  // row-major tiles of each problem
+  std::vector<double> pcost(nsims);                        // estimated cost of one stage
   int64_t woff = 0;
   for (int j = 0; j < nsims; ++j) {
     const nlse_sim_desc& d = sims[j];
@@ -220,31 +218,79 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
       for (int tx = 0; tx < ntx; ++tx) {
         s.tx = tx;
         s.ty = ty;
-        it.push_back(s);
-        cost.push_back(c);
+        tiles[j].push_back(s);
       }
+    pcost[j] = c * (double)tiles[j].size();
   }
-  // contiguous chunks of (problem, tile) items with balanced cost
-  std::vector<int> chunk(B->nchunks + 1, (int)items);
+  // Schedule: contiguous chunks of (problem, tile) items with balanced cost,
+  // one per workgroup.  Problems are independent, so a problem inside one
+  // chunk needs no barrier with any other chunk; a problem spread over
+  // chunks c_a..c_b is a group whose chunks meet at a barrier after every
+  // stage.  Only a chunk's first and last problem can spread beyond it, so
+  // a chunk belongs to at most two groups.  Consecutive chunk numbers land on
+  // one XCD, so most groups share an L2.
+  const int W = B->nchunks;
+  std::vector<nlse::BatchItem> it;
+  std::vector<double> cost;
+  std::vector<int> owner;  // problem of each item
+  it.reserve((size_t)items);
+  for (int j = 0; j < nsims; ++j) {
+    const double c = pcost[j] / (double)tiles[j].size();
+    for (const auto& t : tiles[j]) {
+      it.push_back(t);
+      cost.push_back(c);
+      owner.push_back(j);
+    }
+  }
+  std::vector<int> chunk(5 * (size_t)W + 1, -1);
   {
     double total = 0;
     for (double c : cost) total += c;
     double acc = 0;
     int k = 0;
     chunk[0] = 0;
-    for (int64_t i = 0; i < items && k + 1 < B->nchunks; ++i) {
+    for (int64_t i = 0; i < items && k + 1 < W; ++i) {
       acc += cost[i];
-      if (acc >= total * (k + 1) / B->nchunks) chunk[++k] = (int)(i + 1);
+      if (acc >= total * (k + 1) / W) chunk[++k] = (int)(i + 1);
     }
-    for (int r = k + 1; r < B->nchunks; ++r) chunk[r] = (int)items;
-    chunk[B->nchunks] = (int)items;
+    for (int r = k + 1; r < W; ++r) chunk[r] = (int)items;
+    chunk[W] = (int)items;
+  }
+  // chunk span of every problem, then its group
+  std::vector<int> first(nsims, -1), last(nsims, -1);
+  for (int c = 0; c < W; ++c)
+    for (int i = chunk[c]; i < chunk[c + 1]; ++i) {
+      const int j = owner[i];
+      if (first[j] < 0) first[j] = c;
+      last[j] = c;
+    }
+  int ngroups = 0;
+  std::vector<int> gid(nsims, -1);
+  for (int j = 0; j < nsims; ++j)
+    if (first[j] >= 0 && last[j] > first[j]) gid[j] = ngroups++;
+  for (int c = 0; c < W; ++c) {
+    int ga = -1, gb = -1;
+    if (chunk[c] < chunk[c + 1]) {
+      const int ja = owner[chunk[c]], jb = owner[chunk[c + 1] - 1];
+      ga = gid[ja];
+      gb = (jb != ja) ? gid[jb] : -1;
+      chunk[W + 1 + 4 * c + 1] = ga >= 0 ? last[ja] - first[ja] + 1 : 0;
+      chunk[W + 1 + 4 * c + 3] = gb >= 0 ? last[jb] - first[jb] + 1 : 0;
+    }
+    chunk[W + 1 + 4 * c + 0] = ga;
+    chunk[W + 1 + 4 * c + 2] = gb;
+  }
+  B->ngroups = ngroups;
+  if ((int64_t)it.size() != items) {
+    delete B;
+    return nlse_fail(NLSE_EDEVICE, "internal error: schedule lost work items");
   }
   hipStream_t st = B->stream;
   e = hipMemcpyAsync(B->work + L.items, it.data(), sizeof(nlse::BatchItem) * it.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(B->work + L.chunks, chunk.data(), sizeof(int) * chunk.size(), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.zero, 256, st);
-  if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.barrier, 256, st);
+  if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.barrier, (int64_t)(L.zero - L.barrier), st);
   if (e == hipSuccess && (flags & NLSE_COMPENSATED)) e = nlse_launch_fill_zero(B->work + L.lo, tot * 8, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess && !(flags & NLSE_NO_GRAPH)) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);

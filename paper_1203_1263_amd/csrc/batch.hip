@@ -5,12 +5,15 @@
 // persistent: its grid is sized to what the device holds at once, and each
 // workgroup owns a fixed, cost-balanced chunk of (problem, tile) work items
 // computed on the host.  For every stage a workgroup runs the 2D tile body of
-// the single-grid kernel (tile2d.hpp) on each of its items, then all
-// workgroups meet at a grid-wide barrier before the next stage (a stage of a
-// problem reads the previous stage of its neighbouring tiles).  The barrier
-// is a monotonically increasing arrival counter with a bounded wait: a wait
-// that exceeds the spin limit raises an error flag and every workgroup then
-// leaves the kernel, so the grid always drains.
+// the single-grid kernel (tile2d.hpp) on each of its items, then waits for
+// the workgroups its next stage depends on (a stage of a problem reads the
+// previous stage of its neighbouring tiles).  Problems are independent: a
+// problem inside one chunk needs only a workgroup barrier between stages,
+// and a problem spread over consecutive chunks is a group whose chunks meet
+// at a barrier (a monotonically increasing arrival counter per group with a
+// bounded wait).  A chunk belongs to at most two groups (its first and last
+// problem).  A wait that exceeds the spin limit raises an error flag and
+// every waiting workgroup then leaves the kernel, so the grid always drains.
 //
 // Within a stage the items of a chunk are software-pipelined: while item i
 // is computed, the loads of item i+1 are in flight in a second register set
@@ -29,7 +32,9 @@ namespace nlse {
 template <typename T>
 struct BatchArgs {
   const BatchItem* items;
-  const int* chunk_off;  // items of chunk c: [chunk_off[c], chunk_off[c+1])
+  const int* chunk_off;  // items of chunk c: [chunk_off[c], chunk_off[c+1]);
+                         // then per chunk (group a, size a, group b, size b),
+                         // -1 for no group
   cpx<T>* psi;           // caller's pool
   const T* vpool;        // caller's potential pool (may be null)
   const T* vzero;        // one zero element
@@ -37,36 +42,47 @@ struct BatchArgs {
   cpx<T>* bufA;
   cpx<T>* bufB;
   cpx<T>* lo;
-  unsigned* barrier;     // [0] arrival counter, [1] error flag
+  unsigned* barrier;     // [1] error flag, [2 + g] arrivals of group g
   unsigned spin_limit;
 };
 
-// Grid-wide barrier number `k` (1, 2, ...): every workgroup adds one arrival
-// and waits for k * gridDim.x arrivals.  Only thread 0 crosses device scope:
+// Barrier number `k` (1, 2, ...) of the groups (ga, size sa) and (gb, size
+// sb) a chunk belongs to (-1: none): the workgroup adds one arrival to each
+// group's counter and waits until each holds k * size arrivals.  One
+// release before the arrivals and one acquire after the waits, and only
+// thread 0 crosses device scope:
 // the workgroup barrier first orders every wave's stores before thread 0's
 // agent-scope release (on this chip a release writes back the XCD's L2 and
 // an acquire invalidates it, so one of each per workgroup instead of one
 // per wave), and the workgroup barrier after thread 0's agent-scope acquire
 // orders every wave's later loads after it.  Returns false if the wait
 // timed out or another workgroup reported an error.
-__device__ __forceinline__ bool grid_barrier(unsigned* bar, unsigned k, unsigned spin_limit) {
+__device__ __forceinline__ bool group_barrier(unsigned* bar, int ga, unsigned sa, int gb, unsigned sb, unsigned k,
+                                              unsigned spin_limit) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned target = k * gridDim.x;
-    __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned* flag = bar + 1;
+    unsigned* ca = bar + 2 + (ga >= 0 ? ga : 0);
+    unsigned* cb = bar + 2 + (gb >= 0 ? gb : 0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (ga >= 0) __hip_atomic_fetch_add(ca, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gb >= 0) __hip_atomic_fetch_add(cb, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    auto arrived = [&](const unsigned* c, int g, unsigned size) {
+      return g < 0 || __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= k * size;
+    };
     unsigned spins = 0;
     int good = 1;
     // poll with relaxed loads (an acquire per poll would invalidate the
     // caches under the workgroups still computing); acquire once below
-    while (__hip_atomic_load(&bar[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > spin_limit) {
+    while (!(arrived(ca, ga, sa) && arrived(cb, gb, sb))) {
+      if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > spin_limit) {
         good = 0;
         break;
       }
       __builtin_amdgcn_s_sleep(2);
     }
-    if (!good) __hip_atomic_store(&bar[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!good) __hip_atomic_store(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     ok = good;
   }
@@ -210,16 +226,28 @@ __global__ __launch_bounds__(kBatchTX* kBatchTY) void batch2d_kernel(BatchArgs<T
   __shared__ BatchLds<T> S;
   const int c = xcd_swizzle(blockIdx.x, gridDim.x);
   const int i0 = B.chunk_off[c], i1 = B.chunk_off[c + 1];
+  const int* meta = B.chunk_off + gridDim.x + 1 + 4 * c;
+  const int ga = meta[0], gb = meta[2];
+  const unsigned sa = (unsigned)meta[1], sb = (unsigned)meta[3];
   unsigned k = 0;
+  // a chunk whose problems all lie inside it reads only its own earlier
+  // stores: a workgroup barrier orders them
+  auto sync = [&]() -> bool {
+    if (ga < 0 && gb < 0) {
+      __syncthreads();
+      return true;
+    }
+    return group_barrier(B.barrier, ga, sa, gb, sb, ++k, B.spin_limit);
+  };
   for (int n = 0; n < nsteps; ++n) {
     batch_stage<T, 1, COMP>(B, i0, i1, S);
-    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    if (!sync()) return;
     batch_stage<T, 2, COMP>(B, i0, i1, S);
-    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    if (!sync()) return;
     batch_stage<T, 3, COMP>(B, i0, i1, S);
-    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    if (!sync()) return;
     batch_stage<T, 4, COMP>(B, i0, i1, S);
-    if (!grid_barrier(B.barrier, ++k, B.spin_limit)) return;
+    if (!sync()) return;
   }
 }
 

@@ -28,7 +28,8 @@ static_assert(sizeof(BatchItem) == 128, "BatchItem is read as 32 dwords");
 struct BatchLaunch {
   int dtype, comp, nsteps, nchunks;
   const BatchItem* items;
-  const int* chunk_off;
+  const int* chunk_off;  // nchunks + 1 item offsets, then per chunk its group
+                         // (-1: the chunk owns whole problems), then the group size
   void* psi;
   const void* vpool;
   const void* vzero;
