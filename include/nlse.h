@@ -230,16 +230,19 @@ int nlse_batch_create(nlse_batch **b, int nsims, const nlse_sim_desc *sims,
                       void *hip_stream);
 
 /* Advance every problem nsteps RK4 steps with its own dt (asynchronous, one
- * persistent launch).  A stuck grid-wide barrier (bounded wait) sets an
- * error flag read by nlse_batch_status. */
+ * persistent launch).  Workgroups that share a problem meet at a barrier
+ * after every stage; a wait there is bounded (about 2^25 polls, or the
+ * value of $NLSE_BATCH_SPIN_LIMIT read at creation), and one that runs out
+ * sets an error flag read by nlse_batch_status, after which every waiting
+ * workgroup leaves the kernel. */
 int nlse_batch_step_rk4(nlse_batch *b, int64_t nsteps);
 
 /* Per-problem mass and energy (as nlse_mass_energy, with each problem's own
  * order and bc) into host arrays of nsims doubles.  Synchronises. */
 int nlse_batch_mass_energy(nlse_batch *b, double *mass, double *energy);
 
-/* Synchronises; NLSE_EDEVICE if a grid-wide barrier of the persistent
- * kernel timed out since creation, else NLSE_OK. */
+/* Synchronises; NLSE_EDEVICE if a barrier of the persistent kernel timed
+ * out since creation (the fields are then not valid), else NLSE_OK. */
 int nlse_batch_status(nlse_batch *b);
 
 /* info[0..3] = workgroups of the persistent launch, work items, total grid

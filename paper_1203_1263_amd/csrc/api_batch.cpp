@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -89,6 +90,7 @@ struct nlse_batch {
   std::vector<nlse_sim_desc> desc;
   int64_t total_pts, nitems;
   int nchunks, ngroups;
+  unsigned spin_limit;
   void* psi;
   const void* vpool;
   char* work;
@@ -127,7 +129,7 @@ static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
   L.bufB = b->work + b->lay.bufB;
   L.lo = L.comp ? b->work + b->lay.lo : nullptr;
   L.barrier = reinterpret_cast<unsigned*>(b->work + b->lay.barrier);
-  L.spin_limit = kSpinLimit;
+  L.spin_limit = b->spin_limit;
   return nlse_launch_batch(L, st);
 }
 
@@ -179,6 +181,11 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   B->total_pts = tot;
   B->nitems = items;
   B->nchunks = (int)nchunks;
+  B->spin_limit = kSpinLimit;
+  if (const char* sl = getenv("NLSE_BATCH_SPIN_LIMIT")) {
+    const long v = strtol(sl, nullptr, 10);
+    if (v > 0 && v <= (long)kSpinLimit) B->spin_limit = (unsigned)v;  // a shorter wait only
+  }
   B->psi = psi_pool;
   B->vpool = v_pool;
   B->work = static_cast<char*>(work_dev);

@@ -99,6 +99,33 @@ def test_graph_replays_match_direct_launches():
     graph.status()
 
 
+def test_barrier_timeout_is_reported_and_the_grid_drains(monkeypatch):
+    """A wait at a group barrier that runs out (forced from the host: a spin
+    limit of one poll) sets the error flag; the launch still completes,
+    nlse_batch_status reports NLSE_EDEVICE, and a later launch of the same
+    batch completes too (waiting workgroups leave at once)."""
+    import torch
+    from paper_1203_1263_amd import nlse
+    from paper_1203_1263_amd.nlse import Batch
+    probs, dts = small_batch()
+    monkeypatch.setenv("NLSE_BATCH_SPIN_LIMIT", "1")
+    b = Batch(probs, dts, compensated=True)
+    monkeypatch.delenv("NLSE_BATCH_SPIN_LIMIT")
+    b.step(5)
+    torch.cuda.synchronize()
+    with pytest.raises(nlse.NLSEError) as e:
+        b.status()
+    assert e.value.code == nlse.NLSE_EDEVICE
+    b.step(3)
+    torch.cuda.synchronize()
+    with pytest.raises(nlse.NLSEError):
+        b.status()
+    # a batch created without the override is unaffected
+    b2 = Batch(probs, dts, compensated=True)
+    b2.step(5)
+    b2.status()
+
+
 def test_batch_info_and_schedule():
     from paper_1203_1263_amd.nlse import Batch
     probs, dts = small_batch()
