@@ -483,18 +483,28 @@ extern "C" int nlse_run_frames(nlse_grid* g, int order, int bc, double dt, int64
     if (r == hipSuccess) r = hipEventRecord(g->copied[k], g->copy);
     return r;
   };
+  // on an error, let copies already queued into the caller's buffer finish
+  // before returning (the caller may free it)
+  auto drain = [&]() { (void)hipStreamSynchronize(g->copy); };
   for (int64_t j = 0; j < nframes; ++j) {
     const int k = (int)(j & 1);
     rc = nlse_step_rk4(g, order, bc, dt, chunk);
-    if (rc) return rc;
+    if (rc) {
+      drain();
+      return rc;
+    }
     if (j >= 2) e = hipEventSynchronize(g->copied[k]);  // frame j-2 has left half k
     if (e == hipSuccess) e = nlse_launch_copy(stage + k * fb, g->psi, (int64_t)fb, g->stream);
     if (e == hipSuccess) e = hipEventRecord(g->snap[k], g->stream);
     if (e == hipSuccess && j >= 1) e = copy_out(j - 1);
-    if (e != hipSuccess) return hip_fail(e, "frame copy");
+    if (e != hipSuccess) {
+      drain();
+      return hip_fail(e, "frame copy");
+    }
   }
   e = copy_out(nframes - 1);
   if (e == hipSuccess) e = hipStreamSynchronize(g->copy);
+  else drain();
   if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
   return e == hipSuccess ? NLSE_OK : hip_fail(e, "frame synchronisation");
 }

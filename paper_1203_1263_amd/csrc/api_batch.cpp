@@ -138,6 +138,133 @@ static void destroy_graphs(nlse_batch* b) {
   b->graphs.clear();
 }
 
+// Work items and the static schedule of a batch (host only): the tiles of
+// every problem as device descriptors, and for W chunks the item offsets
+// (W + 1) followed by four ints per chunk (group a, size a, group b,
+// size b; -1 / 0 for none).  Returns the number of groups.
+static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, std::vector<nlse::BatchItem>& it,
+                         std::vector<int>& chunk) {
+  // device descriptors: the same double constants the single-grid path uses
+  std::vector<std::vector<nlse::BatchItem>> tiles(nsims);  // row-major tiles of each problem
+  std::vector<double> pcost(nsims);                        // estimated cost of one stage
+  int64_t woff = 0;
+  for (int j = 0; j < nsims; ++j) {
+    const nlse_sim_desc& d = sims[j];
+    nlse::BatchItem s;
+    std::memset(&s, 0, sizeof s);
+    s.nx = (int)d.dims[0];
+    s.ny = (int)d.dims[1];
+    s.order = d.order;
+    s.bc = d.bc;
+    s.psi_off = d.psi_offset;
+    s.v_off = d.v_offset;
+    s.woff = woff;
+    woff += d.dims[0] * d.dims[1];
+    s.a = d.a;
+    s.s = d.s;
+    s.inv_a = 1.0 / d.a;
+    s.inv_h2 = 1.0 / (d.h * d.h);
+    s.inv_6h2 = 1.0 / (6.0 * d.h * d.h);
+    s.dt = d.dt;
+    s.dt2 = d.dt / 2.0;
+    s.dt3 = d.dt / 3.0;
+    s.dt6 = d.dt / 6.0;
+    s.sim = j;
+    const int ntx = (s.nx + nlse::kBatchTX - 1) / nlse::kBatchTX, nty = (s.ny + nlse::kBatchTY - 1) / nlse::kBatchTY;
+    const double c = (d.order == 4 ? 1.35 : 1.0) * (d.v_offset >= 0 ? 1.1 : 1.0);
+    for (int ty = 0; ty < nty; ++ty)
+      for (int tx = 0; tx < ntx; ++tx) {
+        s.tx = tx;
+        s.ty = ty;
+        tiles[j].push_back(s);
+      }
+    pcost[j] = c * (double)tiles[j].size();
+  }
+  // Schedule: contiguous chunks of (problem, tile) items with balanced cost,
+  // one per workgroup.  Problems are independent, so a problem inside one
+  // chunk needs no barrier with any other chunk; a problem spread over
+  // chunks c_a..c_b is a group whose chunks meet at a barrier after every
+  // stage.  Only a chunk's first and last problem can spread beyond it, so
+  // a chunk belongs to at most two groups.  Consecutive chunk numbers land on
+  // one XCD, so most groups share an L2.
+  it.clear();
+  std::vector<double> cost;
+  std::vector<int> owner;  // problem of each item
+  for (int j = 0; j < nsims; ++j) {
+    const double c = pcost[j] / (double)tiles[j].size();
+    for (const auto& t : tiles[j]) {
+      it.push_back(t);
+      cost.push_back(c);
+      owner.push_back(j);
+    }
+  }
+  const int64_t items = (int64_t)it.size();
+  chunk.assign(5 * (size_t)W + 1, -1);
+  {
+    double total = 0;
+    for (double c : cost) total += c;
+    double acc = 0;
+    int k = 0;
+    chunk[0] = 0;
+    for (int64_t i = 0; i < items && k + 1 < W; ++i) {
+      acc += cost[i];
+      if (acc >= total * (k + 1) / W) chunk[++k] = (int)(i + 1);
+    }
+    for (int r = k + 1; r < W; ++r) chunk[r] = (int)items;
+    chunk[W] = (int)items;
+  }
+  // chunk span of every problem, then its group
+  std::vector<int> first(nsims, -1), last(nsims, -1);
+  for (int c = 0; c < W; ++c)
+    for (int i = chunk[c]; i < chunk[c + 1]; ++i) {
+      const int j = owner[i];
+      if (first[j] < 0) first[j] = c;
+      last[j] = c;
+    }
+  int ngroups = 0;
+  std::vector<int> gid(nsims, -1);
+  for (int j = 0; j < nsims; ++j)
+    if (first[j] >= 0 && last[j] > first[j]) gid[j] = ngroups++;
+  for (int c = 0; c < W; ++c) {
+    int ga = -1, gb = -1;
+    if (chunk[c] < chunk[c + 1]) {
+      const int ja = owner[chunk[c]], jb = owner[chunk[c + 1] - 1];
+      ga = gid[ja];
+      gb = (jb != ja) ? gid[jb] : -1;
+      chunk[W + 1 + 4 * c + 1] = ga >= 0 ? last[ja] - first[ja] + 1 : 0;
+      chunk[W + 1 + 4 * c + 3] = gb >= 0 ? last[jb] - first[jb] + 1 : 0;
+    }
+    chunk[W + 1 + 4 * c + 0] = ga;
+    chunk[W + 1 + 4 * c + 2] = gb;
+  }
+  return ngroups;
+}
+
+// Test hook (host only, no device work): the schedule nlse_batch_create
+// builds for W chunks.  chunk_out receives 5 W + 1 ints (see plan_schedule),
+// item_out 3 ints per work item (problem, tx, ty), *ngroups the number of
+// groups.  NLSE_ENOMEM if an output is shorter than that.
+extern "C" int nlse_internal_batch_plan(int nsims, const nlse_sim_desc* sims, int W, int* chunk_out,
+                                        int64_t chunk_len, int* item_out, int64_t item_len, int* ngroups) {
+  int64_t tot, items, mb;
+  int rc = validate(nsims, sims, NLSE_F32, 0, &tot, &items, &mb);
+  if (rc) return rc;
+  if (W < 1 || W > kMaxChunks || !chunk_out || !item_out || !ngroups) return nlse_fail(NLSE_EINVAL, "bad argument");
+  std::vector<nlse::BatchItem> it;
+  std::vector<int> chunk;
+  const int ng = plan_schedule(nsims, sims, W, it, chunk);
+  if ((int64_t)chunk.size() > chunk_len || 3 * (int64_t)it.size() > item_len)
+    return nlse_fail(NLSE_ENOMEM, "output arrays too short");
+  std::copy(chunk.begin(), chunk.end(), chunk_out);
+  for (size_t i = 0; i < it.size(); ++i) {
+    item_out[3 * i] = it[i].sim;
+    item_out[3 * i + 1] = it[i].tx;
+    item_out[3 * i + 2] = it[i].ty;
+  }
+  *ngroups = ng;
+  return NLSE_OK;
+}
+
 extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags,
                                  void* psi_pool, size_t psi_pool_elems, const void* v_pool, size_t v_pool_elems,
                                  void* work_dev, size_t work_bytes, void* hip_stream) {
@@ -193,100 +320,9 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   B->stream = static_cast<hipStream_t>(hip_stream);
   B->cap = nullptr;
 
-  // device descriptors: the same double constants the single-grid path uses
-  std::vector<std::vector<nlse::BatchItem>> tiles(nsims);  // row-major tiles of each problem
-  std::vector<double> pcost(nsims);                        // estimated cost of one stage
-  int64_t woff = 0;
-  for (int j = 0; j < nsims; ++j) {
-    const nlse_sim_desc& d = sims[j];
-    nlse::BatchItem s;
-    std::memset(&s, 0, sizeof s);
-    s.nx = (int)d.dims[0];
-    s.ny = (int)d.dims[1];
-    s.order = d.order;
-    s.bc = d.bc;
-    s.psi_off = d.psi_offset;
-    s.v_off = d.v_offset;
-    s.woff = woff;
-    woff += d.dims[0] * d.dims[1];
-    s.a = d.a;
-    s.s = d.s;
-    s.inv_a = 1.0 / d.a;
-    s.inv_h2 = 1.0 / (d.h * d.h);
-    s.inv_6h2 = 1.0 / (6.0 * d.h * d.h);
-    s.dt = d.dt;
-    s.dt2 = d.dt / 2.0;
-    s.dt3 = d.dt / 3.0;
-    s.dt6 = d.dt / 6.0;
-    s.sim = j;
-    const int ntx = (s.nx + nlse::kBatchTX - 1) / nlse::kBatchTX, nty = (s.ny + nlse::kBatchTY - 1) / nlse::kBatchTY;
-    const double c = (d.order == 4 ? 1.35 : 1.0) * (d.v_offset >= 0 ? 1.1 : 1.0);
-    for (int ty = 0; ty < nty; ++ty)
-      for (int tx = 0; tx < ntx; ++tx) {
-        s.tx = tx;
-        s.ty = ty;
-        tiles[j].push_back(s);
-      }
-    pcost[j] = c * (double)tiles[j].size();
-  }
-  // Schedule: contiguous chunks of (problem, tile) items with balanced cost,
-  // one per workgroup.  Problems are independent, so a problem inside one
-  // chunk needs no barrier with any other chunk; a problem spread over
-  // chunks c_a..c_b is a group whose chunks meet at a barrier after every
-  // stage.  Only a chunk's first and last problem can spread beyond it, so
-  // a chunk belongs to at most two groups.  Consecutive chunk numbers land on
-  // one XCD, so most groups share an L2.
-  const int W = B->nchunks;
   std::vector<nlse::BatchItem> it;
-  std::vector<double> cost;
-  std::vector<int> owner;  // problem of each item
-  it.reserve((size_t)items);
-  for (int j = 0; j < nsims; ++j) {
-    const double c = pcost[j] / (double)tiles[j].size();
-    for (const auto& t : tiles[j]) {
-      it.push_back(t);
-      cost.push_back(c);
-      owner.push_back(j);
-    }
-  }
-  std::vector<int> chunk(5 * (size_t)W + 1, -1);
-  {
-    double total = 0;
-    for (double c : cost) total += c;
-    double acc = 0;
-    int k = 0;
-    chunk[0] = 0;
-    for (int64_t i = 0; i < items && k + 1 < W; ++i) {
-      acc += cost[i];
-      if (acc >= total * (k + 1) / W) chunk[++k] = (int)(i + 1);
-    }
-    for (int r = k + 1; r < W; ++r) chunk[r] = (int)items;
-    chunk[W] = (int)items;
-  }
-  // chunk span of every problem, then its group
-  std::vector<int> first(nsims, -1), last(nsims, -1);
-  for (int c = 0; c < W; ++c)
-    for (int i = chunk[c]; i < chunk[c + 1]; ++i) {
-      const int j = owner[i];
-      if (first[j] < 0) first[j] = c;
-      last[j] = c;
-    }
-  int ngroups = 0;
-  std::vector<int> gid(nsims, -1);
-  for (int j = 0; j < nsims; ++j)
-    if (first[j] >= 0 && last[j] > first[j]) gid[j] = ngroups++;
-  for (int c = 0; c < W; ++c) {
-    int ga = -1, gb = -1;
-    if (chunk[c] < chunk[c + 1]) {
-      const int ja = owner[chunk[c]], jb = owner[chunk[c + 1] - 1];
-      ga = gid[ja];
-      gb = (jb != ja) ? gid[jb] : -1;
-      chunk[W + 1 + 4 * c + 1] = ga >= 0 ? last[ja] - first[ja] + 1 : 0;
-      chunk[W + 1 + 4 * c + 3] = gb >= 0 ? last[jb] - first[jb] + 1 : 0;
-    }
-    chunk[W + 1 + 4 * c + 0] = ga;
-    chunk[W + 1 + 4 * c + 2] = gb;
-  }
+  std::vector<int> chunk;
+  const int ngroups = plan_schedule(nsims, sims, B->nchunks, it, chunk);
   B->ngroups = ngroups;
   if ((int64_t)it.size() != items) {
     delete B;

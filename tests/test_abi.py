@@ -4,6 +4,8 @@ touches the device."""
 import ctypes
 import math
 
+import numpy as np
+
 import pytest
 
 import oracle
@@ -140,3 +142,73 @@ def test_batch_create_checks_pools_before_launch():
     with pytest.raises(nlse.NLSEError) as e:  # workspace too small
         nlse.nlse_batch_create([_desc()], nlse.NLSE_F32, 0, 4096, 4096, None, 0, 8192, 64, None)
     assert e.value.code == nlse.NLSE_ENOMEM
+
+
+def _plan(descs, W):
+    lib = nlse.load_library()
+    f = lib.nlse_internal_batch_plan
+    f.restype = ctypes.c_int
+    n = len(descs)
+    arr = (nlse.SimDesc * n)(*descs)
+    nitems = sum(((d.dims[0] + 31) // 32) * ((d.dims[1] + 7) // 8) for d in descs)
+    chunk = (ctypes.c_int * (5 * W + 1))()
+    items = (ctypes.c_int * (3 * nitems))()
+    ng = ctypes.c_int()
+    rc = f(n, arr, W, chunk, ctypes.c_int64(5 * W + 1), items, ctypes.c_int64(3 * nitems), ctypes.byref(ng))
+    assert rc == 0, lib.nlse_last_error()
+    c = list(chunk)
+    return c[:W + 1], [tuple(c[W + 1 + 4 * k:W + 5 + 4 * k]) for k in range(W)], list(items), ng.value, nitems
+
+
+@pytest.mark.parametrize("seed,nsims,W", [(0, 40, 64), (1, 512, 768), (2, 7, 200), (3, 3, 1), (4, 30, 4096)])
+def test_batch_schedule_invariants(seed, nsims, W):
+    """The batched integrator's static schedule (host logic): every tile of
+    every problem in exactly one chunk; a problem's tiles in consecutive
+    chunks; a problem spread over several chunks is one group whose size is
+    its chunk span and which every chunk of the span (and no other) names;
+    chunk costs balanced to within one tile of the fair share."""
+    g = np.random.default_rng(seed)
+    sizes = (64, 128, 192, 256, 384, 512) if nsims > 10 else (3, 40, 100, 700)
+    descs, off = [], 0
+    for j in range(nsims):
+        nx, ny = int(g.choice(sizes)), int(g.choice(sizes))
+        descs.append(_desc(dims=(nx, ny, 1), order=int(g.choice([2, 4])), psi_offset=off,
+                           v_offset=-1 if j % 2 else 0))
+        off += nx * ny
+    offs, meta, items, ngroups, nitems = _plan(descs, W)
+    assert offs[0] == 0 and offs[-1] == nitems and all(a <= b for a, b in zip(offs, offs[1:]))
+    trip = [tuple(items[3 * i:3 * i + 3]) for i in range(nitems)]
+    assert len(set(trip)) == nitems  # no tile twice
+    sim = np.array(items[0::3])
+    want = [((d.dims[0] + 31) // 32) * ((d.dims[1] + 7) // 8) for d in descs]
+    assert np.array_equal(np.bincount(sim, minlength=nsims), want)
+    chunk_of = np.searchsorted(np.array(offs), np.arange(nitems), side="right") - 1
+    span = {}
+    for j in range(nsims):
+        cs = np.unique(chunk_of[sim == j]).tolist()
+        assert cs == list(range(cs[0], cs[-1] + 1))  # consecutive chunks
+        span[j] = cs
+    # group a of a chunk belongs to its first problem, group b to its last
+    gid = {}
+    for c in range(W):
+        ga, sa, gb, sb = meta[c]
+        if offs[c] == offs[c + 1]:
+            assert ga < 0 and gb < 0
+            continue
+        ja, jb = trip[offs[c]][0], trip[offs[c + 1] - 1][0]
+        for j, gg, ss in ((ja, ga, sa), (jb, gb, sb) if jb != ja else (None, gb, sb)):
+            if j is None:
+                assert gg < 0
+                continue
+            if len(span[j]) == 1:
+                assert gg < 0
+            else:
+                assert gg >= 0 and ss == len(span[j])
+                assert gid.setdefault(j, gg) == gg  # one group per problem
+    assert sorted(gid.values()) == list(range(ngroups))  # distinct groups, numbered 0..n-1
+    assert set(gid) == {j for j in range(nsims) if len(span[j]) > 1}
+    # balance (cost model of the schedule: 1.35 for 2SHOC, 1.1 with a potential)
+    cost = np.array([(1.35 if descs[t[0]].order == 4 else 1.0) * (1.1 if descs[t[0]].v_offset >= 0 else 1.0)
+                     for t in trip])
+    loads = np.array([cost[offs[c]:offs[c + 1]].sum() for c in range(W)])
+    assert loads.max() <= cost.sum() / W + cost.max() + 1e-9
