@@ -527,6 +527,9 @@ extern "C" int nlse_mass_energy(nlse_grid* g, int order, int bc, double* mass, d
   R.h = g->h;
   R.partials = reinterpret_cast<double*>(g->work + g->lay.partials);
   R.out = reinterpret_cast<double*>(g->work + g->lay.out);
+  // the stage buffers are idle between steps: bufA (and bufB after it, for
+  // FP32) holds the FP64 D of the 2SHOC energy
+  R.dscratch = g->work + g->lay.bufA;
   hipError_t e = nlse_launch_reduce(R, g->stream);
   if (e != hipSuccess) return hip_fail(e, "reduction launch");
   double host[3];

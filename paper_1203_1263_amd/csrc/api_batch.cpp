@@ -397,6 +397,7 @@ extern "C" int nlse_batch_mass_energy(nlse_batch* b, double* mass, double* energ
     R.h = d.h;
     R.partials = reinterpret_cast<double*>(b->work + b->lay.partials);
     R.out = out + 3 * j;
+    R.dscratch = b->work + b->lay.bufA;  // idle between steps; bufB follows it
     hipError_t e = nlse_launch_reduce(R, b->stream);
     if (e != hipSuccess) return nlse_hip_fail(e, "reduction launch");
   }

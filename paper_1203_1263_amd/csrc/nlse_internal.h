@@ -36,6 +36,7 @@ struct ReduceLaunch {
   const void* V;
   double a, s, h;
   double* partials;  // >= reduce_blocks(npts) * 3 doubles
+  void* dscratch;    // order 4: npts complex doubles for the stored 2SHOC D
   double* out;       // 3 doubles: sum rho, sum kinetic, sum potential
 };
 

@@ -11,44 +11,49 @@
 // and a fixed cross-wave order; a single workgroup then sums the partials in
 // a fixed order.  The result is bitwise reproducible and independent of the
 // stage kernels' tile shapes.
+#include <algorithm>
+
 #include "nlse_device.hpp"
 #include "nlse_internal.h"
 
 namespace nlse {
 
-template <typename T>
+// ND (the number of active axes) is a template parameter so every loop over
+// the axes unrolls and the coordinate arrays stay in registers.
+template <typename T, int ND>
 struct View {
   const cpx<T>* u;
   const T* V;
-  int ndim;
   int n[3];
   int64_t st[3];
   double a, s, inv_a, inv_h2, inv_6h2;
 };
 
-template <typename T>
-__device__ __forceinline__ cpx<double> ldd(const View<T>& g, const int c[3]) {
+template <typename T, int ND>
+__device__ __forceinline__ cpx<double> ldd(const View<T, ND>& g, const int c[3]) {
   cpx<T> v = g.u[c[0] * g.st[0] + c[1] * g.st[1] + c[2] * g.st[2]];
   return mk<double>((double)v.re, (double)v.im);
 }
 
-template <typename T>
-__device__ __forceinline__ double vd(const View<T>& g, const int c[3]) {
+template <typename T, int ND>
+__device__ __forceinline__ double vd(const View<T, ND>& g, const int c[3]) {
   return g.V ? (double)g.V[c[0] * g.st[0] + c[1] * g.st[1] + c[2] * g.st[2]] : 0.0;
 }
 
-template <typename T>
-__device__ __forceinline__ bool on_bnd(const View<T>& g, const int c[3]) {
-  for (int d = 0; d < g.ndim; ++d)
+template <typename T, int ND>
+__device__ __forceinline__ bool on_bnd(const View<T, ND>& g, const int c[3]) {
+#pragma unroll
+  for (int d = 0; d < ND; ++d)
     if (c[d] == 0 || c[d] == g.n[d] - 1) return true;
   return false;
 }
 
-template <typename T>
-__device__ cpx<double> cd2_at(const View<T>& g, const int c[3]) {
+template <typename T, int ND>
+__device__ cpx<double> cd2_at(const View<T, ND>& g, const int c[3]) {
   cpx<double> u = ldd(g, c);
   double sr = 0.0, si = 0.0;
-  for (int d = 0; d < g.ndim; ++d) {
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
     int p[3] = {c[0], c[1], c[2]};
     p[d] = c[d] + 1;
     cpx<double> a = ldd(g, p);
@@ -60,14 +65,14 @@ __device__ cpx<double> cd2_at(const View<T>& g, const int c[3]) {
   return mk<double>(sr * g.inv_h2, si * g.inv_h2);
 }
 
-template <typename T>
-__device__ __forceinline__ double nl_d(const View<T>& g, cpx<double> u, double v) {
+template <typename T, int ND>
+__device__ __forceinline__ double nl_d(const View<T, ND>& g, cpx<double> u, double v) {
   return g.s * (u.re * u.re + u.im * u.im) - v;
 }
 
 // 2SHOC step-1 value D at any point: CD2 inside, boundary form on the edge.
-template <typename T>
-__device__ cpx<double> D_at(const View<T>& g, int bc, const int c[3]) {
+template <typename T, int ND>
+__device__ cpx<double> D_at(const View<T, ND>& g, int bc, const int c[3]) {
   if (!on_bnd(g, c)) return cd2_at(g, c);
   if (bc == kL0) return mk<double>(0.0, 0.0);  // Eq. BCL0lap
   cpx<double> ub = ldd(g, c);
@@ -77,7 +82,8 @@ __device__ cpx<double> D_at(const View<T>& g, int bc, const int c[3]) {
     return mk<double>(f * ub.re, f * ub.im);
   }
   int q[3] = {c[0], c[1], c[2]};
-  for (int d = 0; d < g.ndim; ++d) q[d] += inward(c[d], g.n[d]);
+#pragma unroll
+  for (int d = 0; d < ND; ++d) q[d] += inward(c[d], g.n[d]);
   cpx<double> uq = ldd(g, q);
   cpx<double> Dq = cd2_at(g, q);
   double m = uq.re * uq.re + uq.im * uq.im;
@@ -86,24 +92,60 @@ __device__ cpx<double> D_at(const View<T>& g, int bc, const int c[3]) {
   return mk<double>(f * ub.re, f * ub.im);
 }
 
-// Scheme Laplacian at an interior point.
-template <typename T>
-__device__ cpx<double> L_at(const View<T>& g, int order, int bc, const int c[3]) {
+// Coordinates of linear index i (x fastest): 32-bit divisions when the grid
+// has fewer than 2^31 points (64-bit division costs far more).
+template <typename T, int ND>
+__device__ __forceinline__ void coords(const View<T, ND>& g, int64_t i, int c[3]) {
+  if (i <= 0x7fffffff) {
+    const unsigned u = (unsigned)i, n0 = (unsigned)g.n[0], n1 = (unsigned)g.n[1];
+    const unsigned q = u / n0;
+    c[0] = (int)(u - q * n0);
+    c[1] = (int)(q % n1);
+    c[2] = (int)(q / n1);
+  } else {
+    c[0] = (int)(i % g.n[0]);
+    c[1] = (int)((i / g.n[0]) % g.n[1]);
+    c[2] = (int)(i / ((int64_t)g.n[0] * g.n[1]));
+  }
+}
+
+template <typename T, int ND>
+__device__ __forceinline__ int64_t lin(const View<T, ND>& g, const int c[3]) {
+  return c[0] * g.st[0] + c[1] * g.st[1] + c[2] * g.st[2];
+}
+
+// 2SHOC step 1 at every point, stored once (FP64) for the energy pass: the
+// Laplacian of each interior point then reads its own and its 2d
+// neighbours' D instead of recomputing them.
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void reduce_d_kernel(View<T, ND> g, int bc, int64_t npts, cpx<double>* D) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < npts; i += (int64_t)gridDim.x * 256) {
+    int c[3];
+    coords(g, i, c);
+    D[i] = D_at(g, bc, c);
+  }
+}
+
+// Scheme Laplacian at an interior point (2SHOC from the stored D).
+template <typename T, int ND>
+__device__ cpx<double> L_at(const View<T, ND>& g, int order, const cpx<double>* D, const int c[3]) {
   if (order == 2) return cd2_at(g, c);
-  cpx<double> D0 = D_at(g, bc, c);
+  cpx<double> D0 = D[lin(g, c)];
   cpx<double> u0 = ldd(g, c);
   double fr = 0.0, fi = 0.0, er = 0.0, ei = 0.0;
-  for (int d = 0; d < g.ndim; ++d) {
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
     for (int sgn = -1; sgn <= 1; sgn += 2) {
       int p[3] = {c[0], c[1], c[2]};
       p[d] += sgn;
-      cpx<double> Df = D_at(g, bc, p);
+      cpx<double> Df = D[lin(g, p)];
       fr += Df.re - D0.re;
       fi += Df.im - D0.im;
     }
   }
-  for (int d1 = 0; d1 < g.ndim; ++d1)
-    for (int d2 = d1 + 1; d2 < g.ndim; ++d2)
+#pragma unroll
+  for (int d1 = 0; d1 < ND; ++d1)
+    for (int d2 = d1 + 1; d2 < ND; ++d2)
       for (int s1 = -1; s1 <= 1; s1 += 2)
         for (int s2 = -1; s2 <= 1; s2 += 2) {
           int p[3] = {c[0], c[1], c[2]};
@@ -113,7 +155,7 @@ __device__ cpx<double> L_at(const View<T>& g, int order, int bc, const int c[3])
           er += ue.re - u0.re;
           ei += ue.im - u0.im;
         }
-  double c0 = g.ndim == 1 ? 1.0 : (g.ndim == 2 ? 2.0 / 3.0 : 1.0 / 3.0);
+  double c0 = ND == 1 ? 1.0 : (ND == 2 ? 2.0 / 3.0 : 1.0 / 3.0);
   return mk<double>(c0 * D0.re - fr / 12.0 + g.inv_6h2 * er, c0 * D0.im - fi / 12.0 + g.inv_6h2 * ei);
 }
 
@@ -122,24 +164,22 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void reduce_partial_kernel(View<T> g, int order, int bc, int64_t npts,
-                                                             double* partials) {
+template <typename T, int ND>
+__global__ __launch_bounds__(256) void reduce_partial_kernel(View<T, ND> g, int order, const cpx<double>* D,
+                                                             int64_t npts, double* partials) {
   __shared__ double red[3][4];
   const int64_t b0 = (int64_t)blockIdx.x * kReduceChunk;
   const int64_t b1 = min(b0 + (int64_t)kReduceChunk, npts);
   double m = 0.0, kin = 0.0, pot = 0.0;
   for (int64_t i = b0 + threadIdx.x; i < b1; i += 256) {
     int c[3];
-    c[0] = (int)(i % g.n[0]);
-    c[1] = (int)((i / g.n[0]) % g.n[1]);
-    c[2] = (int)(i / ((int64_t)g.n[0] * g.n[1]));
+    coords(g, i, c);
     cpx<double> u = ldd(g, c);
     double rho = u.re * u.re + u.im * u.im;
     m += rho;
     pot += vd(g, c) * rho - 0.5 * g.s * rho * rho;
     if (!on_bnd(g, c)) {
-      cpx<double> L = L_at(g, order, bc, c);
+      cpx<double> L = L_at(g, order, D, c);
       kin += -g.a * (u.re * L.re + u.im * L.im);
     }
   }
@@ -186,12 +226,11 @@ __global__ void copy_words_kernel(const uint2* __restrict__ src, uint2* __restri
   for (; i < n; i += stride) dst[i] = src[i];
 }
 
-template <typename T>
-static hipError_t reduce_typed(const ReduceLaunch& R, hipStream_t st) {
-  View<T> g;
+template <typename T, int ND>
+static hipError_t reduce_dim(const ReduceLaunch& R, hipStream_t st) {
+  View<T, ND> g;
   g.u = static_cast<const cpx<T>*>(R.psi);
   g.V = static_cast<const T*>(R.V);
-  g.ndim = R.ndim;
   for (int d = 0; d < 3; ++d) g.n[d] = (int)R.n[d];
   g.st[0] = 1;
   g.st[1] = R.n[0];
@@ -203,12 +242,31 @@ static hipError_t reduce_typed(const ReduceLaunch& R, hipStream_t st) {
   g.inv_6h2 = 1.0 / (6.0 * R.h * R.h);
   const int64_t npts = R.n[0] * R.n[1] * R.n[2];
   const int64_t nb = reduce_blocks(npts);
-  hipLaunchKernelGGL((reduce_partial_kernel<T>), dim3((unsigned)nb), dim3(256), 0, st, g, R.order, R.bc, npts,
+  cpx<double>* D = nullptr;
+  if (R.order == 4) {
+    if (!R.dscratch) return hipErrorInvalidValue;
+    D = static_cast<cpx<double>*>(R.dscratch);
+    const int64_t blocks = std::min<int64_t>((npts + 255) / 256, 8192);
+    hipLaunchKernelGGL((reduce_d_kernel<T, ND>), dim3((unsigned)blocks), dim3(256), 0, st, g, R.bc, npts, D);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((reduce_partial_kernel<T, ND>), dim3((unsigned)nb), dim3(256), 0, st, g, R.order, D, npts,
                      R.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, R.partials, nb, R.out);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t reduce_typed(const ReduceLaunch& R, hipStream_t st) {
+  switch (R.ndim) {
+    case 1: return reduce_dim<T, 1>(R, st);
+    case 2: return reduce_dim<T, 2>(R, st);
+    case 3: return reduce_dim<T, 3>(R, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace nlse
