@@ -63,6 +63,37 @@ def test_forward_matches_reference():
     assert np.linalg.norm(ref - x64) > 1e-3 * np.linalg.norm(x64)  # the increment is not trivial
 
 
+def test_forward_graph_replays_follow_weight_updates():
+    """The forward pass is captured once per (input, output, batch) and
+    replayed: replays into two outputs, with eager device work between,
+    give the first call's bits; after a training step a replay gives the
+    bits of a model created directly with the updated weights."""
+    import torch
+    from paper_1203_1263_amd.nlse import Surrogate
+    H, W, B = 32, 48, 2
+    m, _, params = make(H, W, B, seed=5)
+    x = torch.from_numpy(fields(B, H, W, 8).astype(np.complex64)).cuda()
+    o1, o2 = torch.empty_like(x), torch.empty_like(x)
+    m.forward(x, o1)
+    first = o1.clone()
+    for k in range(3):
+        junk = (torch.randn(1 << 16, device="cuda") * 2).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        m.forward(x, o2 if k % 2 else o1)
+        torch.cuda.synchronize()
+        assert torch.equal(o2 if k % 2 else o1, first)
+    m.train_step(x, x * np.exp(-0.1j), 1e-2)
+    m.forward(x, o1)
+    torch.cuda.synchronize()
+    assert not torch.equal(o1, first)
+    fresh = Surrogate(H, W, B, 0.25, params=params.clone())
+    ref = fresh.forward(x)
+    torch.cuda.synchronize()
+    assert torch.equal(o1, ref)
+    fresh.close()
+    m.close()
+
+
 def test_gradients_match_reference_and_are_reproducible():
     import torch
     H, W, B = 32, 32, 2
@@ -167,3 +198,40 @@ def test_advance_with_large_tolerance_uses_the_network():
         ref = m.forward(ref.reshape(1, H, W)).reshape(H, W)
     assert nf == 0
     assert torch.equal(a, ref)
+
+
+def test_advance_blocks_replay_and_follow_weight_updates():
+    """An advance block (keep the input, predict, project the MSD ring) is
+    captured once and replayed: three blocks, with eager work between calls,
+    give the bits of explicit forward + projection calls, and after a
+    training step the replayed block uses the new weights."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    H = W = 32
+    m, _, _ = make(H, W, 1, seed=5)
+    x = fields(1, H, W, 15)[0]
+    a = torch.from_numpy(x.astype(np.complex64)).cuda()
+    g = Grid(a, 0.25, 1.0, -1.0)
+
+    def explicit(start, n):
+        ref = start.clone().reshape(1, H, W)
+        for _ in range(n):
+            out = m.forward(ref)
+            m.project_msd(ref, out)
+            ref = out
+        return ref.reshape(H, W)
+
+    for k in range(3):
+        start = a.clone()
+        m.advance(g, 4, "msd", 0.01, 1, 1e9)
+        junk = (torch.randn(1 << 16, device="cuda") * 2).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(a, explicit(start, 1)), k
+    xin = torch.from_numpy(x.astype(np.complex64)).cuda().reshape(1, H, W)
+    m.train_step(xin, xin * np.exp(-0.1j), 1e-2)
+    start = a.clone()
+    m.advance(g, 4, "msd", 0.01, 1, 1e9)
+    torch.cuda.synchronize()
+    assert torch.equal(a, explicit(start, 1))
+    g.close()
+    m.close()
