@@ -444,6 +444,8 @@ extern "C" int nlse_step_rk4(nlse_grid* g, int order, int bc, double dt, int64_t
   return NLSE_OK;
 }
 
+constexpr size_t kZeroCopyFrameMax = 1u << 20;  // bytes per frame
+
 // Frames: after each chunk, Psi is snapshotted on the grid's stream into one
 // half of the staging buffer (a copy kernel), and the copy stream moves that
 // snapshot to the host while the next chunk integrates.  The host orders the
@@ -473,6 +475,29 @@ extern "C" int nlse_run_frames(nlse_grid* g, int order, int bc, double dt, int64
     if (e == hipSuccess && !g->copied[k]) e = hipEventCreateWithFlags(&g->copied[k], hipEventDisableTiming);
   }
   if (e != hipSuccess) return hip_fail(e, "creating the copy stream / events");
+  // Small frames into pinned memory the device can address: the copy kernel
+  // writes each frame straight into host memory on the grid's stream (one
+  // launch per frame, no second stream, no host waits).  Any other buffer
+  // (pageable, or frames too large to copy without overlap) takes the
+  // staged path below.
+  if (fb <= kZeroCopyFrameMax) {
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, frames_host) == hipSuccess && at.type == hipMemoryTypeHost &&
+        at.devicePointer) {
+      char* dst = static_cast<char*>(at.devicePointer);
+      for (int64_t j = 0; j < nframes; ++j) {
+        rc = nlse_step_rk4(g, order, bc, dt, chunk);
+        if (rc) break;
+        e = nlse_launch_copy(dst + j * fb, g->psi, (int64_t)fb, g->stream);
+        if (e != hipSuccess) break;
+      }
+      hipError_t se = hipStreamSynchronize(g->stream);
+      if (rc) return rc;
+      if (e == hipSuccess) e = se;
+      return e == hipSuccess ? NLSE_OK : hip_fail(e, "frame copy");
+    }
+    (void)hipGetLastError();  // an unregistered pointer leaves an error behind
+  }
   char* stage = static_cast<char*>(stage_dev);
   char* host = static_cast<char*>(frames_host);
   // frame j: wait until its snapshot is complete, then copy it out

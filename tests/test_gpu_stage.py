@@ -205,7 +205,8 @@ def test_graph_replay_equals_direct_launches(shape, dtype, order, bc, comp, fuse
 
 
 FRAME_CASES = [((37, 150), "f32", True, 7, True), ((37, 150), "f32", False, 1, False),
-               ((11, 9, 70), "f64", False, 3, True), ((600,), "f32", True, 2, True)]
+               ((11, 9, 70), "f64", False, 3, True), ((600,), "f32", True, 2, True),
+               ((200, 800), "f32", True, 3, True)]  # 1.28 MB frames: the staged, overlapped path
 
 
 @pytest.mark.parametrize("shape,dtype,comp,chunk,pinned", FRAME_CASES,
@@ -213,9 +214,10 @@ FRAME_CASES = [((37, 150), "f32", True, 7, True), ((37, 150), "f32", False, 1, F
                               for c in FRAME_CASES])
 def test_frames_equal_stepwise_fields(shape, dtype, comp, chunk, pinned):
     """nlse_run_frames delivers, after every chunk, the field that the same
-    number of nlse_step_rk4 steps produces (bitwise), with pinned and pageable
-    host buffers and with more frames than staging halves; the field left on
-    the device is the last frame."""
+    number of nlse_step_rk4 steps produces (bitwise): small frames written
+    straight into pinned memory, larger ones staged and overlapped, pageable
+    buffers, more frames than staging halves; the field left on the device
+    is the last frame."""
     import torch
     from paper_1203_1263_amd import nlse
     from paper_1203_1263_amd.nlse import Grid
