@@ -67,7 +67,7 @@ enum { kEpiRelu = 0, kEpiLast = 1, kEpiDgrad = 2 };
 // LDS rows are padded by 16 bytes (weights: K + 8, pixels: CIN + 8 BF16
 // values) so the 16-byte operand reads of 16 lanes hit distinct banks.
 template <int CIN, int COUT, int EPI>
-__global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntiles) {
+__global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles) {
   constexpr int K = 9 * CIN;
   constexpr int KP = K + 8;    // padded weight row
   constexpr int CP = CIN + 8;  // padded input pixel
@@ -145,13 +145,13 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntiles) {
 #pragma unroll
       for (int rr = 0; rr < 4; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-#pragma unroll 2
-    for (int ks = 0; ks < KSTEPS; ++ks) {
+    // operands of k-step ks (weights: 16 output channels x 32 k; input: 32 k
+    // x 16 pixels of one row), read from LDS
+    auto frags = [&](int ks, bf16x8 (&af)[NCB], bf16x8 (&bfr)[4]) {
       const int k0 = 32 * ks + 8 * g;
       const bool kv = k0 < K;
       const int tap = kv ? k0 / CIN : 0, ci0 = kv ? k0 % CIN : 0;
       const int dy = tap / 3, dx = tap - 3 * dy;
-      bf16x8 af[NCB], bfr[4];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
         af[cb] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * KP + k0]) : zero4());
@@ -160,12 +160,27 @@ __global__ __launch_bounds__(256) void conv3x3_kernel(ConvArgs a, int ntiles) {
         const int row = 4 * wave + rr;
         bfr[rr] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sIn[((row + dy) * 18 + j + dx) * CP + ci0]) : zero4());
       }
+    };
+    auto mfmas = [&](const bf16x8 (&af)[NCB], const bf16x8 (&bfr)[4]) {
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr)
           acc[cb][rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cb], bfr[rr], acc[cb][rr], 0, 0, 0);
+    };
+    // two operand sets: the reads of step ks+1 are in flight while the
+    // matrix cores work on step ks (each accumulator still sums the k-steps
+    // in ascending order)
+    bf16x8 a0[NCB], b0[4], a1[NCB], b1[4];
+    frags(0, a0, b0);
+    int ks = 0;
+    for (; ks + 1 < KSTEPS; ks += 2) {
+      frags(ks + 1, a1, b1);
+      mfmas(a0, b0);
+      if (ks + 2 < KSTEPS) frags(ks + 2, a0, b0);
+      mfmas(a1, b1);
     }
+    if (ks < KSTEPS) mfmas(a0, b0);
 
     // lane holds D[co = 16 cb + 4 g + r][pixel (row, j)], r = 0..3
 #pragma unroll
