@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
   f32x4 acc[PER];
 #pragma unroll
   for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-  float bacc = 0.f;  // bias partial of channel tid (tid < COUT)
+  float bacc = 0.f;  // bias partial of channel tid / 4 (lanes with tid % 4 == 0, tid < 4 COUT)
 
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int b = t / (tilesx * tilesy);
@@ -315,10 +315,18 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
       for (int q = 0; q < 8; ++q) sZ[(part * 8 + q) * 128 + pp] = e[q];
     }
     __syncthreads();
-    if (tid < COUT) {
+    // bias gradient: four lanes per channel (lanes 4c .. 4c+3 of the first
+    // 4 COUT threads) sum 32 pixels each, then two fixed-order shuffles
+    {
       float s = 0.f;
-      for (int p = 0; p < 128; ++p) s += bf16_val(sZ[tid * 128 + p]);
-      bacc += s;
+      if (tid < 4 * COUT) {
+        const uint16_t* z = &sZ[(tid >> 2) * 128 + 32 * (tid & 3)];
+#pragma unroll 8
+        for (int p = 0; p < 32; ++p) s += bf16_val(z[p]);
+      }
+      s += __shfl_xor(s, 1, 64);
+      s += __shfl_xor(s, 2, 64);
+      if (tid < 4 * COUT && (tid & 3) == 0) bacc += s;
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) P[(16 * mb + 4 * g + r) * (N + 1) + n] = acc[q][r];
   }
-  if (tid < COUT) P[tid * (N + 1) + N] = bacc;
+  if (tid < 4 * COUT && (tid & 3) == 0) P[(tid >> 2) * (N + 1) + N] = bacc;
 }
 
 // Fixed-order sum of the partials into the canonical gradient of one layer:
