@@ -367,11 +367,17 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
 
 // Fixed-order sum of the partials into the canonical gradient of one layer:
 // W (Cout, Cin, 3, 3) then b (Cout), real channels only.
-__global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int nparts, int coutp, int cinp, int cout,
-                                    int cin, float* __restrict__ gw, float* __restrict__ gb) {
+// One wave per gradient entry: lane l sums parts l, l + 64, ... in order,
+// then a fixed shuffle tree adds the 64 lane sums (deterministic; the loads
+// of a wave are independent, where one thread per entry waited for each of
+// its 512 strided loads in turn).
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ partial, int nparts,
+                                                           int coutp, int cinp, int cout, int cin,
+                                                           float* __restrict__ gw, float* __restrict__ gb) {
   const int N = 9 * cinp;
   const int total = cout * (9 * cin + 1);
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  for (int e = blockIdx.x * 4 + (threadIdx.x >> 6); e < total; e += gridDim.x * 4) {
     int co, col;
     const bool is_b = e >= cout * 9 * cin;
     if (is_b) {
@@ -384,11 +390,14 @@ __global__ void wgrad_reduce_kernel(const float* __restrict__ partial, int npart
       col = tap * cinp + ci;
     }
     double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += (double)partial[((int64_t)p * coutp + co) * (N + 1) + col];
-    if (is_b)
-      gb[co] = (float)s;
-    else
-      gw[e] = (float)s;
+    for (int p = lane; p < nparts; p += 64) s += (double)partial[((int64_t)p * coutp + co) * (N + 1) + col];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+      if (is_b)
+        gb[co] = (float)s;
+      else
+        gw[e] = (float)s;
+    }
   }
 }
 
@@ -590,7 +599,7 @@ hipError_t sg_wgrad(int kind, const uint16_t* a, const uint16_t* dz, float* part
 hipError_t sg_wgrad_reduce(const float* partial, int nparts, int coutp, int cinp, int cout, int cin, float* gw,
                            float* gb, hipStream_t st) {
   const int total = cout * (9 * cin + 1);
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, st, partial, nparts, coutp, cinp,
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + 3) / 4), dim3(256), 0, st, partial, nparts, coutp, cinp,
                      cout, cin, gw, gb);
   return hipGetLastError();
 }
