@@ -421,7 +421,7 @@ extern "C" int nlse_batch_status(nlse_batch* b) {
   hipError_t e = hipMemcpyAsync(flag, b->work + b->lay.barrier, sizeof flag, hipMemcpyDeviceToHost, b->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return nlse_hip_fail(e, "reading the batch status");
-  return flag[1] ? nlse_fail(NLSE_EDEVICE, "a grid-wide barrier of the batched kernel timed out") : NLSE_OK;
+  return flag[1] ? nlse_fail(NLSE_EDEVICE, "a barrier of the batched kernel timed out") : NLSE_OK;
 }
 
 extern "C" int nlse_batch_info(const nlse_batch* b, int64_t info[4]) {
