@@ -266,8 +266,12 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
   constexpr int NBLK = MB * NB;
   constexpr int PER = (NBLK + 3) / 4;  // output blocks per wave
   constexpr int CH = CIN / 8, CHZ = COUT / 8;
-  __shared__ __attribute__((aligned(16))) uint16_t sA[3 * CIN * 10 * 16];  // [dx][ci][row][col]
-  __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT * 128];          // [co][row][col]
+  // Rows are padded by 8 values (16 bytes) so the 16 lanes of an operand
+  // read (consecutive channels) fall on distinct LDS banks.
+  constexpr int APL = 10 * 16 + 8;  // one (dx, ci) plane of the input tile
+  constexpr int ZPL = 128 + 8;      // one output channel of the gradient tile
+  __shared__ __attribute__((aligned(16))) uint16_t sA[3 * CIN * APL];  // [dx][ci][row][col]
+  __shared__ __attribute__((aligned(16))) uint16_t sZ[COUT * ZPL];     // [co][row][col]
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, g = lane >> 4;
@@ -284,9 +288,11 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
     const int x0 = tx * 16, y0 = ty * 8;
     const int64_t img = (int64_t)b * A.H * A.W;
     __syncthreads();  // previous tile's LDS reads are done
-    // input halo tile (10 rows x 18 cols) -> three x-shifted channel-major copies
+    // input halo tile (10 rows x 18 cols) -> three x-shifted channel-major
+    // copies; consecutive lanes take consecutive pixels of one 8-channel
+    // part, so their 2-byte stores are adjacent
     for (int i = tid; i < 10 * 18 * CH; i += 256) {
-      const int pp = i / CH, part = i - pp * CH;
+      const int part = i / (10 * 18), pp = i - part * (10 * 18);
       const int r = pp / 18, c = pp - r * 18;
       const int gy = y0 - 1 + r, gx = x0 - 1 + c;
       uint4 v = zero4();
@@ -300,19 +306,20 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
         const int cc = c - dx;
         if (cc < 0 || cc >= 16) continue;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) sA[((dx * CIN + part * 8 + q) * 10 + r) * 16 + cc] = e[q];
+        for (int q = 0; q < 8; ++q) sA[(dx * CIN + part * 8 + q) * APL + r * 16 + cc] = e[q];
       }
     }
-    // output-gradient tile (8 rows x 16 cols) -> channel-major
+    // output-gradient tile (8 rows x 16 cols) -> channel-major (part-major
+    // lanes as above)
     for (int i = tid; i < 128 * CHZ; i += 256) {
-      const int pp = i / CHZ, part = i - pp * CHZ;
+      const int part = i / 128, pp = i - part * 128;
       const int r = pp / 16, c = pp - r * 16;
       const uint4 v = reinterpret_cast<const uint4*>(A.dz + (img + (int64_t)(y0 + r) * A.W + x0 + c) * COUT)[part];
       const uint16_t e[8] = {(uint16_t)(v.x & 0xffffu), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffffu),
                              (uint16_t)(v.y >> 16), (uint16_t)(v.z & 0xffffu), (uint16_t)(v.z >> 16),
                              (uint16_t)(v.w & 0xffffu), (uint16_t)(v.w >> 16)};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) sZ[(part * 8 + q) * 128 + pp] = e[q];
+      for (int q = 0; q < 8; ++q) sZ[(part * 8 + q) * ZPL + pp] = e[q];
     }
     __syncthreads();
     // bias gradient: four lanes per channel (lanes 4c .. 4c+3 of the first
@@ -320,7 +327,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
     {
       float s = 0.f;
       if (tid < 4 * COUT) {
-        const uint16_t* z = &sZ[(tid >> 2) * 128 + 32 * (tid & 3)];
+        const uint16_t* z = &sZ[(tid >> 2) * ZPL + 32 * (tid & 3)];
 #pragma unroll 8
         for (int p = 0; p < 32; ++p) s += bf16_val(z[p]);
       }
@@ -338,13 +345,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
         if (blk >= NBLK) break;
         const int mb = blk / NB, nb = blk - mb * NB;
         const int co = 16 * mb + j;
-        const bf16x8 af = as_bf16x8(*reinterpret_cast<const uint4*>(&sZ[co * 128 + p0]));
+        const bf16x8 af = as_bf16x8(*reinterpret_cast<const uint4*>(&sZ[co * ZPL + p0]));
         const int n = 16 * nb + j;
         uint4 bv = zero4();
         if (n < N) {
           const int tap = n / CIN, ci = n - tap * CIN;
           const int dy = tap / 3, dx = tap - 3 * dy;
-          bv = *reinterpret_cast<const uint4*>(&sA[((dx * CIN + ci) * 10 + py + dy) * 16 + px]);
+          bv = *reinterpret_cast<const uint4*>(&sA[(dx * CIN + ci) * APL + (py + dy) * 16 + px]);
         }
         acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, as_bf16x8(bv), acc[q], 0, 0, 0);
       }
