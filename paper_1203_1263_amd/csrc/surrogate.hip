@@ -259,12 +259,20 @@ struct WgradArgs {
 // db[co] = sum_pixels dz[p][co].  Tiles of 16 x 8 pixels; workgroup w takes
 // tiles w, w + G, w + 2G, ... in order, so each partial has a fixed order.
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
+__global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs A) {
   constexpr int N = 9 * CIN;
   constexpr int NB = (N + 15) / 16;
   constexpr int MB = COUT / 16;
   constexpr int NBLK = MB * NB;
   constexpr int PER = (NBLK + 3) / 4;  // output blocks per wave
+  // With many column blocks, wave w owns column blocks w, w + 4, ... for
+  // every row block: one B fragment read from LDS then feeds MB MFMAs and
+  // each A fragment is read once per k-step (LDS read bandwidth, not the
+  // MFMAs, bounds this loop otherwise).  Each accumulator still takes the
+  // same MFMAs in the same order.
+  constexpr bool BYCOL = NB >= 8;
+  constexpr int QN = (NB + 3) / 4;
+  constexpr int NACC = BYCOL ? QN * MB : PER;
   constexpr int CH = CIN / 8, CHZ = COUT / 8;
   // Rows are padded by 8 values (16 bytes) so the 16 lanes of an operand
   // read (consecutive channels) fall on distinct LDS banks.
@@ -277,27 +285,58 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
   const int j = lane & 15, g = lane >> 4;
   const int tilesx = A.W / 16, tilesy = A.H / 8;
   const int ntiles = A.B * tilesx * tilesy;
-  f32x4 acc[PER];
+  f32x4 acc[NACC];
 #pragma unroll
-  for (int q = 0; q < PER; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < NACC; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bacc = 0.f;  // bias partial of channel tid / 4 (lanes with tid % 4 == 0, tid < 4 COUT)
 
-  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+  // Tile staging in two halves: the global loads of tile t + G are issued
+  // into registers before the MFMAs of tile t and written to LDS (unpacked
+  // into the channel-major layouts) after them, so their latency is hidden.
+  constexpr int AITEMS = 10 * 18 * CH, ZITEMS = 128 * CHZ;
+  constexpr int NA = (AITEMS + 255) / 256, NZ = (ZITEMS + 255) / 256;
+  uint4 ra[NA], rz[NZ];
+  auto gload = [&](int t) {
     const int b = t / (tilesx * tilesy);
     const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
     const int x0 = tx * 16, y0 = ty * 8;
     const int64_t img = (int64_t)b * A.H * A.W;
-    __syncthreads();  // previous tile's LDS reads are done
-    // input halo tile (10 rows x 18 cols) -> three x-shifted channel-major
-    // copies; consecutive lanes take consecutive pixels of one 8-channel
-    // part, so their 2-byte stores are adjacent
-    for (int i = tid; i < 10 * 18 * CH; i += 256) {
+    // input halo tile (10 rows x 18 cols); consecutive lanes take
+    // consecutive pixels of one 8-channel part
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const int i = tid + 256 * k;
+      ra[k] = zero4();
+      if (i < AITEMS) {
+        const int part = i / (10 * 18), pp = i - part * (10 * 18);
+        const int r = pp / 18, c = pp - r * 18;
+        const int gy = y0 - 1 + r, gx = x0 - 1 + c;
+        if (gy >= 0 && gy < A.H && gx >= 0 && gx < A.W)
+          ra[k] = reinterpret_cast<const uint4*>(A.a + (img + (int64_t)gy * A.W + gx) * CIN)[part];
+      }
+    }
+    // output-gradient tile (8 rows x 16 cols)
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+      const int i = tid + 256 * k;
+      rz[k] = zero4();
+      if (i < ZITEMS) {
+        const int part = i / 128, pp = i - part * 128;
+        const int r = pp / 16, c = pp - r * 16;
+        rz[k] = reinterpret_cast<const uint4*>(A.dz + (img + (int64_t)(y0 + r) * A.W + x0 + c) * COUT)[part];
+      }
+    }
+  };
+  auto lstore = [&]() {
+    // three x-shifted channel-major copies of the input tile; adjacent lanes'
+    // 2-byte stores are adjacent
+#pragma unroll
+    for (int k = 0; k < NA; ++k) {
+      const int i = tid + 256 * k;
+      if (i >= AITEMS) break;
       const int part = i / (10 * 18), pp = i - part * (10 * 18);
       const int r = pp / 18, c = pp - r * 18;
-      const int gy = y0 - 1 + r, gx = x0 - 1 + c;
-      uint4 v = zero4();
-      if (gy >= 0 && gy < A.H && gx >= 0 && gx < A.W)
-        v = reinterpret_cast<const uint4*>(A.a + (img + (int64_t)gy * A.W + gx) * CIN)[part];
+      const uint4 v = ra[k];
       const uint16_t e[8] = {(uint16_t)(v.x & 0xffffu), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffffu),
                              (uint16_t)(v.y >> 16), (uint16_t)(v.z & 0xffffu), (uint16_t)(v.z >> 16),
                              (uint16_t)(v.w & 0xffffu), (uint16_t)(v.w >> 16)};
@@ -309,19 +348,27 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
         for (int q = 0; q < 8; ++q) sA[(dx * CIN + part * 8 + q) * APL + r * 16 + cc] = e[q];
       }
     }
-    // output-gradient tile (8 rows x 16 cols) -> channel-major (part-major
-    // lanes as above)
-    for (int i = tid; i < 128 * CHZ; i += 256) {
+    // the output-gradient tile, channel-major
+#pragma unroll
+    for (int k = 0; k < NZ; ++k) {
+      const int i = tid + 256 * k;
+      if (i >= ZITEMS) break;
       const int part = i / 128, pp = i - part * 128;
-      const int r = pp / 16, c = pp - r * 16;
-      const uint4 v = reinterpret_cast<const uint4*>(A.dz + (img + (int64_t)(y0 + r) * A.W + x0 + c) * COUT)[part];
+      const uint4 v = rz[k];
       const uint16_t e[8] = {(uint16_t)(v.x & 0xffffu), (uint16_t)(v.x >> 16), (uint16_t)(v.y & 0xffffu),
                              (uint16_t)(v.y >> 16), (uint16_t)(v.z & 0xffffu), (uint16_t)(v.z >> 16),
                              (uint16_t)(v.w & 0xffffu), (uint16_t)(v.w >> 16)};
 #pragma unroll
       for (int q = 0; q < 8; ++q) sZ[(part * 8 + q) * ZPL + pp] = e[q];
     }
+  };
+
+  if ((int)blockIdx.x < ntiles) gload(blockIdx.x);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    __syncthreads();  // previous tile's LDS reads are done
+    lstore();
     __syncthreads();
+    if (t + (int)gridDim.x < ntiles) gload(t + gridDim.x);
     // bias gradient: four lanes per channel (lanes 4c .. 4c+3 of the first
     // 4 COUT threads) sum 32 pixels each, then two fixed-order shuffles
     {
@@ -339,13 +386,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
     for (int ks = 0; ks < 4; ++ks) {
       const int p0 = 32 * ks + 8 * g;  // 8 consecutive pixels in one row
       const int py = p0 >> 4, px = p0 & 15;
-#pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int blk = wave + 4 * q;
-        if (blk >= NBLK) break;
-        const int mb = blk / NB, nb = blk - mb * NB;
-        const int co = 16 * mb + j;
-        const bf16x8 af = as_bf16x8(*reinterpret_cast<const uint4*>(&sZ[co * ZPL + p0]));
+      auto bfrag = [&](int nb) {
         const int n = 16 * nb + j;
         uint4 bv = zero4();
         if (n < N) {
@@ -353,17 +394,49 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs A) {
           const int dy = tap / 3, dx = tap - 3 * dy;
           bv = *reinterpret_cast<const uint4*>(&sA[(dx * CIN + ci) * APL + (py + dy) * 16 + px]);
         }
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, as_bf16x8(bv), acc[q], 0, 0, 0);
+        return as_bf16x8(bv);
+      };
+      if constexpr (BYCOL) {
+        bf16x8 af[MB];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+          af[mb] = as_bf16x8(*reinterpret_cast<const uint4*>(&sZ[(16 * mb + j) * ZPL + p0]));
+#pragma unroll
+        for (int qn = 0; qn < QN; ++qn) {
+          const int nb = wave + 4 * qn;
+          if (nb >= NB) break;
+          const bf16x8 bf = bfrag(nb);
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb)
+            acc[qn * MB + mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[mb], bf, acc[qn * MB + mb], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int blk = wave + 4 * q;
+          if (blk >= NBLK) break;
+          const int mb = blk / NB, nb = blk - mb * NB;
+          const bf16x8 af = as_bf16x8(*reinterpret_cast<const uint4*>(&sZ[(16 * mb + j) * ZPL + p0]));
+          acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfrag(nb), acc[q], 0, 0, 0);
+        }
       }
     }
   }
   // lane holds D[co = 16 mb + 4 g + r][n = 16 nb + j]
   float* P = A.partial + (int64_t)blockIdx.x * COUT * (N + 1);
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int blk = wave + 4 * q;
-    if (blk >= NBLK) break;
-    const int mb = blk / NB, nb = blk - mb * NB;
+  for (int q = 0; q < NACC; ++q) {
+    int mb, nb;
+    if constexpr (BYCOL) {
+      mb = q % MB;
+      nb = wave + 4 * (q / MB);
+      if (nb >= NB) break;
+    } else {
+      const int blk = wave + 4 * q;
+      if (blk >= NBLK) break;
+      mb = blk / NB;
+      nb = blk - mb * NB;
+    }
     const int n = 16 * nb + j;
     if (n < N)
 #pragma unroll
