@@ -446,37 +446,38 @@ __global__ __launch_bounds__(256, 2) void wgrad_kernel(WgradArgs A) {
 }
 
 // Fixed-order sum of the partials into the canonical gradient of one layer:
-// W (Cout, Cin, 3, 3) then b (Cout), real channels only.
-// One wave per gradient entry: lane l sums parts l, l + 64, ... in order,
-// then a fixed shuffle tree adds the 64 lane sums (deterministic; the loads
-// of a wave are independent, where one thread per entry waited for each of
-// its 512 strided loads in turn).
-__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ partial, int nparts,
+// W (Cout, Cin, 3, 3) then b (Cout), real channels only.  A workgroup takes
+// 64 consecutive partial columns of one output channel; wave w sums parts
+// w, w + 8, ... in ascending order (each load of a wave is one contiguous
+// 256-byte row of one part), then wave 0 adds the 8 wave sums in order.
+// The result depends only on nparts, not on timing.
+__global__ __launch_bounds__(512) void wgrad_reduce_kernel(const float* __restrict__ partial, int nparts,
                                                            int coutp, int cinp, int cout, int cin,
                                                            float* __restrict__ gw, float* __restrict__ gb) {
+  __shared__ double red[8][64];
   const int N = 9 * cinp;
-  const int total = cout * (9 * cin + 1);
-  const int lane = threadIdx.x & 63;
-  for (int e = blockIdx.x * 4 + (threadIdx.x >> 6); e < total; e += gridDim.x * 4) {
-    int co, col;
-    const bool is_b = e >= cout * 9 * cin;
-    if (is_b) {
-      co = e - cout * 9 * cin;
-      col = N;
+  const int nblk = (N + 1 + 63) / 64;
+  const int co = blockIdx.x / nblk;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = (blockIdx.x - co * nblk) * 64 + lane;
+  double s = 0.0;
+  if (col <= N) {
+    const float* src = partial + (int64_t)co * (N + 1) + col;
+    const int64_t stride = (int64_t)coutp * (N + 1);
+#pragma unroll 8
+    for (int p = w; p < nparts; p += 8) s += (double)src[p * stride];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && col <= N) {
+    double t = red[0][lane];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) t += red[k][lane];
+    if (col == N) {
+      gb[co] = (float)t;
     } else {
-      co = e / (9 * cin);
-      const int rem = e - co * 9 * cin;  // (ci, ky, kx)
-      const int ci = rem / 9, tap = rem - ci * 9;
-      col = tap * cinp + ci;
-    }
-    double s = 0.0;
-    for (int p = lane; p < nparts; p += 64) s += (double)partial[((int64_t)p * coutp + co) * (N + 1) + col];
-    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) {
-      if (is_b)
-        gb[co] = (float)s;
-      else
-        gw[e] = (float)s;
+      const int tap = col / cinp, ci = col - tap * cinp;
+      if (ci < cin) gw[(co * cin + ci) * 9 + tap] = (float)t;
     }
   }
 }
@@ -678,9 +679,10 @@ hipError_t sg_wgrad(int kind, const uint16_t* a, const uint16_t* dz, float* part
 
 hipError_t sg_wgrad_reduce(const float* partial, int nparts, int coutp, int cinp, int cout, int cin, float* gw,
                            float* gb, hipStream_t st) {
-  const int total = cout * (9 * cin + 1);
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((total + 3) / 4), dim3(256), 0, st, partial, nparts, coutp, cinp,
-                     cout, cin, gw, gb);
+  if (cout < 1 || cout > coutp || cin < 1 || cin > cinp || nparts < 1) return hipErrorInvalidValue;
+  const int nblk = (9 * cinp + 1 + 63) / 64;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(cout * nblk), dim3(512), 0, st, partial, nparts, coutp, cinp, cout,
+                     cin, gw, gb);
   return hipGetLastError();
 }
 
