@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--plain", action="store_true", help="plain FP32 (no compensation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=0,
-                    help="oracle steps for the CPU baseline (0 = pick ~15 s of work)")
+                    help="oracle steps of each CPU-baseline run (0: 40 on all cores, 6 on one)")
     ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("TX", "TY", "CZ"),
                     help="stage tile (default: the library's default tile)")
     ap.add_argument("--autotune", action="store_true", help="let the autotuner pick the tile")
@@ -60,6 +60,7 @@ def parse():
                          "surrogate: train the 16-step surrogate and time it against RK4")
     ap.add_argument("--trajectories", type=int, default=200, help="surrogate: trajectories of 100 pairs")
     ap.add_argument("--iters", type=int, default=3000, help="surrogate: Adam iterations")
+    ap.add_argument("--cpu-child", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -148,30 +149,81 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(problem, dt, steps_hint):
-    """Time the FP64 oracle as it stands on a bounded sample of the workload."""
+def _cpu_info():
+    """Host CPU description: model name, logical CPUs this process may use,
+    physical cores (distinct core ids per socket)."""
+    model, phys = None, set()
+    cur = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    if cur:
+                        phys.add((cur.get("physical id"), cur.get("core id")))
+                    cur = {}
+                    continue
+                k, v = (t.strip() for t in line.split(":", 1))
+                cur[k] = v
+                if k == "model name" and model is None:
+                    model = v
+        if cur:
+            phys.add((cur.get("physical id"), cur.get("core id")))
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": nproc, "physical_cores": len(phys) or None}
+
+
+def _oracle_child(threads, steps, n):
+    """Run the oracle in a child process with its own OpenMP settings (the
+    thread count is fixed when the OpenMP runtime starts); returns
+    (point-updates/s, seconds, steps)."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS=str(threads), OMP_PROC_BIND="close", OMP_PLACES="cores")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", str(steps), "--n", str(n)]
+    r = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_child(steps, n):
+    """Child of cpu_baseline: time the FP64 oracle on the bench workload."""
     import oracle
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = steps_hint if steps_hint > 0 else 0
-    if n == 0:
-        # one calibration step, then enough steps for ~15 s of CPU work
-        t0 = time.perf_counter()
-        oracle.rk4(problem.psi0, problem.h, problem.a, problem.s, dt, 1, V=problem.V,
-                   order=problem.order, bc=problem.bc)
-        one = time.perf_counter() - t0
-        n = max(1, min(50, int(15.0 / max(one, 1e-3))))
+    from paper_1203_1263_amd import workloads as wl
+    prob = wl.ring3d(shape=(n, n, n), h=0.1 * 256 / n)
+    dt = 0.8 * oracle.dt_max(3, 4, prob.h, prob.a)
     t0 = time.perf_counter()
-    oracle.rk4(problem.psi0, problem.h, problem.a, problem.s, dt, n, V=problem.V,
-               order=problem.order, bc=problem.bc)
+    oracle.rk4(prob.psi0, prob.h, prob.a, prob.s, dt, steps, V=prob.V, order=prob.order, bc=prob.bc)
     el = time.perf_counter() - t0
-    return {"value": problem.npts * n / el, "unit": "grid-point RK4 updates/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{'x'.join(map(str, problem.psi0.shape[::-1]))} grid, {n} RK4 steps, "
-                      f"2SHOC+MSD, FP64, {cores} OpenMP threads, {el:.1f} s"}
+    print(json.dumps({"rate": prob.npts * steps / el, "seconds": el, "steps": steps}), flush=True)
+
+
+def cpu_baseline(steps_hint, n):
+    """Time the FP64 oracle as it stands on a bounded sample of the bench
+    workload (256^3, 2SHOC + MSD), once on one thread and once on all the
+    cores this host gives the job (OMP_NUM_THREADS if set, else its physical
+    cores), each in a child process with OMP_PROC_BIND=close."""
+    info = _cpu_info()
+    share = int(os.environ.get("OMP_NUM_THREADS", 0) or 0)
+    threads = share if share > 0 else (info["physical_cores"] or info["nproc"])
+    many = _oracle_child(threads, steps_hint if steps_hint > 0 else 40, n)
+    one = _oracle_child(1, steps_hint if steps_hint > 0 else 6, n)
+    shape = f"{n}x{n}x{n} grid, 2SHOC+MSD, FP64"
+    return {"value": many["rate"], "unit": "grid-point RK4 updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{shape}, {many['steps']} RK4 steps on {threads} OpenMP threads "
+                      f"(OMP_PROC_BIND=close), {many['seconds']:.1f} s",
+            "single_core": {"value": one["rate"], "cores": 1,
+                            "sample": f"{shape}, {one['steps']} RK4 steps on 1 thread, {one['seconds']:.1f} s"},
+            **info}
 
 
 def main():
     args = parse()
+    if args.cpu_child:
+        cpu_child(args.cpu_child, args.n)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -203,6 +255,9 @@ def main():
     elif args.autotune:
         g.autotune(NLSE_2SHOC, "msd", dt)
     tile = g.tile(NLSE_2SHOC)
+    # warm-up: the timed call's own step count first, so every graph it
+    # replays is captured and instantiated before the timed region
+    g.step(dt, args.steps, order=NLSE_2SHOC, bc="msd")
     g.step(dt, args.warmup, order=NLSE_2SHOC, bc="msd")
     torch.cuda.synchronize()
 
@@ -250,7 +305,7 @@ def main():
         "mass": M, "energy": E,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, float(dt), args.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_steps, n)
     g.close()
     print(json.dumps(out), flush=True)
 

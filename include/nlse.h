@@ -230,8 +230,10 @@ int nlse_batch_create(nlse_batch **b, int nsims, const nlse_sim_desc *sims,
                       void *hip_stream);
 
 /* Advance every problem nsteps RK4 steps with its own dt (asynchronous, one
- * persistent launch).  Workgroups that share a problem meet at a barrier
- * after every stage; a wait there is bounded (about 2^25 polls, or the
+ * persistent launch), 0 <= nsteps <= 2^24 (NLSE_EINVAL otherwise, checked
+ * first).  Workgroups that share a problem meet at a barrier after every
+ * stage, counted in 64-bit arrival counters (the last target of a call,
+ * 4 nsteps x group size, cannot wrap); a wait there is bounded (about 2^25 polls, or the
  * value of $NLSE_BATCH_SPIN_LIMIT read at creation), and one that runs out
  * sets an error flag read by nlse_batch_status, after which every waiting
  * workgroup leaves the kernel. */

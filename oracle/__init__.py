@@ -14,7 +14,7 @@ Functions (each cites the passage of the paper it follows, in the C source):
   Dirichlet / MSD / Laplacian-zero boundary forms (Sec. "Boundary
   conditions").
 * :func:`laplacian` -- the scheme Laplacian alone at interior points.
-* :func:`rk4` -- classic RK4 in the ten-step ordering of Eq. RK4.
+* :func:`rk4` -- classic RK4 (Eq. RK4) with its four slopes k_1..k_4.
 * :func:`mass_energy` -- standard NLSE invariants (not defined by the paper).
 
 Arrays are complex128 numpy arrays of shape ``(Nz, Ny, Nx)``, ``(Ny, Nx)`` or

@@ -17,7 +17,8 @@
  *     Eq. BCDdt and Laplacian form Eq. BCDlap; modulus-squared Dirichlet (MSD),
  *     time form Eq. msd and Laplacian form Eq. BCMSDlap; Laplacian-zero (L0),
  *     time form Eq. BCL0dt and Laplacian form Eq. BCL0lap;
- *   - classic RK4 in the textbook ten-step ordering of Eq. RK4;
+ *   - classic RK4 (Eq. RK4) with its four slopes k_1..k_4 and weights
+ *     1/6, 1/3, 1/3, 1/6;
  *   - the linear stability bounds, Eqs. stblincd and stblin2shoc;
  *   - discrete mass and energy (the paper defines neither; the standard NLSE
  *     invariants are used, see orc_mass_energy).
@@ -344,12 +345,12 @@ int orc_laplacian(int ndim, const long *n, double h, double a, double s,
     return ORC_OK;
 }
 
-/* nsteps of classic RK4 in the ten-step ordering of Eq. RK4, in place:
- *  1) Ktot = F(Psi^n)          6) Ktmp = F(Psi_tmp)
- *  2) Psi_tmp = Psi^n + k/2 Ktot   7) Ktot = Ktot + 2 Ktmp
- *  3) Ktmp = F(Psi_tmp)        8) Psi_tmp = Psi^n + k Ktmp
- *  4) Ktot = Ktot + 2 Ktmp     9) Ktmp = F(Psi_tmp)
- *  5) Psi_tmp = Psi^n + k/2 Ktmp  10) Psi^{n+1} = Psi^n + k/6 (Ktot + Ktmp) */
+/* nsteps of the classic fourth-order Runge-Kutta method (Sec. "Fourth-order
+ * Runge-Kutta", Eq. RK4), in place, written with its four slopes:
+ *   k_1 = F(Psi),  k_2 = F(Psi + (dt/2) k_1),  k_3 = F(Psi + (dt/2) k_2),
+ *   k_4 = F(Psi + dt k_3),  Psi <- Psi + (dt/6)(k_1 + 2 k_2 + 2 k_3 + k_4).
+ * Each slope is a full-grid evaluation of F with its boundary forms; the
+ * argument of the next slope is formed from the unchanged Psi. */
 int orc_rk4(int ndim, const long *n, double h, double a, double s,
             const double *V, int order, int bc, double dt, long nsteps,
             double *psi)
@@ -360,37 +361,39 @@ int orc_rk4(int ndim, const long *n, double h, double a, double s,
     if ((rc = check_scheme(order, bc))) return rc;
     if (!(dt > 0) || nsteps < 0) return ORC_EINVAL;
     long m = 2 * g.npts;
-    double *Ktot = calloc(m, sizeof(double));
-    double *Ktmp = calloc(m, sizeof(double));
-    double *tmp = calloc(m, sizeof(double));
+    /* stage offsets c_2..c_4 of the Butcher tableau, as fractions of dt */
+    const double c[4] = {0.0, 0.5, 0.5, 1.0};
+    double *k[4] = {NULL, NULL, NULL, NULL};
+    double *arg = calloc(m, sizeof(double));
     double *L = calloc(m, sizeof(double));
     double *D = calloc(m, sizeof(double));
-    if (!Ktot || !Ktmp || !tmp || !L || !D) {
-        free(Ktot); free(Ktmp); free(tmp); free(L); free(D);
+    int ok = arg && L && D;
+    for (int j = 0; j < 4; ++j) {
+        k[j] = calloc(m, sizeof(double));
+        ok = ok && k[j];
+    }
+    if (!ok) {
+        for (int j = 0; j < 4; ++j) free(k[j]);
+        free(arg); free(L); free(D);
         return ORC_ENOMEM;
     }
     for (long it = 0; it < nsteps; ++it) {
-        compute_F(&g, order, bc, psi, Ktot, L, D);                 /* 1 */
+        compute_F(&g, order, bc, psi, k[0], L, D);
+        for (int j = 1; j < 4; ++j) {
+            const double *prev = k[j - 1];
+            const double step = c[j] * dt;
 #pragma omp parallel for schedule(static)
-        for (long i = 0; i < m; ++i) tmp[i] = psi[i] + (dt / 2.0) * Ktot[i]; /* 2 */
-        compute_F(&g, order, bc, tmp, Ktmp, L, D);                 /* 3 */
+            for (long i = 0; i < m; ++i) arg[i] = psi[i] + step * prev[i];
+            compute_F(&g, order, bc, arg, k[j], L, D);
+        }
 #pragma omp parallel for schedule(static)
         for (long i = 0; i < m; ++i) {
-            Ktot[i] = Ktot[i] + 2.0 * Ktmp[i];                     /* 4 */
-            tmp[i] = psi[i] + (dt / 2.0) * Ktmp[i];                /* 5 */
+            double slope = k[0][i] + 2.0 * k[1][i] + 2.0 * k[2][i] + k[3][i];
+            psi[i] = psi[i] + (dt / 6.0) * slope;
         }
-        compute_F(&g, order, bc, tmp, Ktmp, L, D);                 /* 6 */
-#pragma omp parallel for schedule(static)
-        for (long i = 0; i < m; ++i) {
-            Ktot[i] = Ktot[i] + 2.0 * Ktmp[i];                     /* 7 */
-            tmp[i] = psi[i] + dt * Ktmp[i];                        /* 8 */
-        }
-        compute_F(&g, order, bc, tmp, Ktmp, L, D);                 /* 9 */
-#pragma omp parallel for schedule(static)
-        for (long i = 0; i < m; ++i)
-            psi[i] = psi[i] + (dt / 6.0) * (Ktot[i] + Ktmp[i]);   /* 10 */
     }
-    free(Ktot); free(Ktmp); free(tmp); free(L); free(D);
+    for (int j = 0; j < 4; ++j) free(k[j]);
+    free(arg); free(L); free(D);
     return ORC_OK;
 }
 

@@ -17,7 +17,16 @@ Channels 2 -> 48 -> 48 -> 48 -> 48 -> 48 -> 2.  W_l has shape
 z[y, x, co] = sum_{ci, ky, kx} a[y + ky - 1, x + kx - 1, ci] W[co, ci, ky, kx].
 Loss: mean over batch, pixels and the 2 channels of (pred - target)^2.
 
-Everything is plain NumPy in float64, written for clarity, not speed.
+Everything is float64 on the CPU: NumPy for the network's bookkeeping and
+PyTorch's CPU cross-correlation for the 3x3 convolutions (a library primitive;
+the sums it evaluates are written out in conv3x3 / conv3x3_grad).
+
+Optionally (``bf16=True``) the values the network stores are rounded to
+bfloat16 where a BF16 implementation stores them: the input channels, the
+weights, the hidden activations and the back-propagated output gradients.
+The sums themselves stay in float64.  This is the same network evaluated on
+BF16-quantised operands, so the rounding decisions, not the arithmetic, are
+those of a BF16 kernel.
 """
 from __future__ import annotations
 
@@ -53,30 +62,51 @@ def pack(params) -> np.ndarray:
     return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params])
 
 
+def to_bf16(x):
+    """Round to the nearest bfloat16 value, ties to even, returned as float64.
+
+    bfloat16 keeps the sign, the 8 exponent bits and the top 7 fraction bits
+    of an IEEE binary32 value; rounding adds half of the dropped 16-bit field
+    (minus one unless the kept field is odd) before truncating.  Values are
+    first rounded to binary32.  Non-finite inputs are not expected."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    r = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+
+
 def conv3x3(a, W, b=None):
-    """Zero-padded 3x3 cross-correlation. a: (B, H, W, Cin), W: (Cout, Cin, 3, 3)."""
-    Bn, H, Wd, _ = a.shape
-    ap = np.zeros((Bn, H + 2, Wd + 2, a.shape[3]))
-    ap[:, 1:-1, 1:-1, :] = a
-    z = np.zeros((Bn, H, Wd, W.shape[0]))
-    for ky in range(3):
-        for kx in range(3):
-            z += ap[:, ky:ky + H, kx:kx + Wd, :] @ W[:, :, ky, kx].T
+    """Zero-padded 3x3 cross-correlation. a: (B, H, W, Cin), W: (Cout, Cin, 3, 3).
+
+    z[b, y, x, co] = sum_{ci, ky, kx} a[b, y + ky - 1, x + kx - 1, ci] W[co, ci, ky, kx]
+    (out-of-range a taken as 0), evaluated in FP64 by the CPU library
+    cross-correlation of PyTorch."""
+    import torch.nn.functional as F
+    z = F.conv2d(_t(a).permute(0, 3, 1, 2), _t(W), padding=1).permute(0, 2, 3, 1).numpy()
+    z = np.ascontiguousarray(z)
     if b is not None:
         z += b
     return z
 
 
-def forward(params, psi):
-    """psi: complex (B, H, W).  Returns pred and the cache for backward."""
-    a = np.stack([psi.real, psi.imag], axis=-1).astype(np.float64)
+def forward(params, psi, bf16=False):
+    """psi: complex (B, H, W).  Returns pred and the cache for backward.
+    With bf16, the input channels, weights and hidden activations are
+    rounded to bfloat16 (to_bf16) where they are stored."""
+    q = to_bf16 if bf16 else (lambda v: v)
+    a = q(np.stack([psi.real, psi.imag], axis=-1).astype(np.float64))
     acts, zs = [a], []
     n = len(params)
     for l, (W, b) in enumerate(params):
-        z = conv3x3(acts[-1], W, b)
+        z = conv3x3(acts[-1], q(W), b)
         zs.append(z)
         if l < n - 1:
-            acts.append(np.maximum(z, 0.0))
+            acts.append(q(np.maximum(z, 0.0)))
     z6 = zs[-1]
     pred = psi + (z6[..., 0] + 1j * z6[..., 1])
     return pred, (acts, zs)
@@ -89,34 +119,43 @@ def loss(params, psi, target):
 
 
 def conv3x3_grad(a, W, dz):
-    """Gradients of z = conv3x3(a, W) + b: returns (da, dW, db)."""
-    Bn, H, Wd, Cin = a.shape
-    ap = np.zeros((Bn, H + 2, Wd + 2, Cin))
-    ap[:, 1:-1, 1:-1, :] = a
-    dW = np.zeros_like(W)
-    dap = np.zeros_like(ap)
-    for ky in range(3):
-        for kx in range(3):
-            win = ap[:, ky:ky + H, kx:kx + Wd, :]
-            dW[:, :, ky, kx] = np.einsum("bhwo,bhwi->oi", dz, win)
-            dap[:, ky:ky + H, kx:kx + Wd, :] += dz @ W[:, :, ky, kx]
-    db = dz.sum(axis=(0, 1, 2))
-    return dap[:, 1:-1, 1:-1, :], dW, db
+    """Gradients of z = conv3x3(a, W) + b: returns (da, dW, db).
+
+    da[b, y, x, ci] = sum_{co, ky, kx} dz[b, y - ky + 1, x - kx + 1, co] W[co, ci, ky, kx]
+    (the cross-correlation of dz with the point-reflected, channel-transposed
+    kernel), dW[co, ci, ky, kx] = sum_{b, y, x} dz[b, y, x, co] a[b, y + ky - 1, x + kx - 1, ci],
+    db[co] = sum_{b, y, x} dz[b, y, x, co]; FP64, PyTorch CPU library
+    correlations."""
+    import torch.nn.functional as F
+    dzt = _t(dz).permute(0, 3, 1, 2)
+    Wt = _t(W)
+    da = F.conv2d(dzt, Wt.flip(2, 3).transpose(0, 1), padding=1).permute(0, 2, 3, 1).numpy()
+    # dW as the correlation of the input channels with the output gradients,
+    # batch folded into the reduction
+    at = _t(a).permute(3, 0, 1, 2)           # (Cin, B, H, W)
+    dW = F.conv2d(at, dzt.transpose(0, 1), padding=1)  # (Cin, Cout, 3, 3)
+    dW = dW.transpose(0, 1).numpy()
+    db = np.asarray(dz, dtype=np.float64).sum(axis=(0, 1, 2))
+    return np.ascontiguousarray(da), np.ascontiguousarray(dW), db
 
 
-def loss_and_grad(params, psi, target):
-    """MSE loss and its gradient w.r.t. every (W, b), by backpropagation."""
-    pred, (acts, zs) = forward(params, psi)
+def loss_and_grad(params, psi, target, bf16=False):
+    """MSE loss and its gradient w.r.t. every (W, b), by backpropagation.
+    With bf16, forward as above, and the output gradients of every layer are
+    rounded to bfloat16 where they are stored; the input gradient of a layer
+    is taken with its rounded weights and masked by its rounded activation."""
+    q = to_bf16 if bf16 else (lambda v: v)
+    pred, (acts, zs) = forward(params, psi, bf16)
     d = pred - target
     nel = 2 * d.size
-    dz = np.stack([d.real, d.imag], axis=-1) * (2.0 / nel)
+    dz = q(np.stack([d.real, d.imag], axis=-1) * (2.0 / nel))
     grads = [None] * len(params)
     for l in range(len(params) - 1, -1, -1):
         W, _ = params[l]
-        da, dW, db = conv3x3_grad(acts[l], W, dz)
+        da, dW, db = conv3x3_grad(acts[l], q(W), dz)
         grads[l] = (dW, db)
         if l > 0:
-            dz = da * (zs[l - 1] > 0)
+            dz = q(da * (acts[l] > 0))
     L = float(np.mean(np.concatenate([d.real.ravel(), d.imag.ravel()]) ** 2))
     return L, grads
 

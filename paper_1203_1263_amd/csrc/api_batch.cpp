@@ -21,6 +21,8 @@ namespace {
 constexpr int kMaxChunks = 8192;          // upper bound of persistent workgroups
 constexpr unsigned kSpinLimit = 1u << 25; // bounded barrier wait (~1-2 s)
 constexpr int kMaxWgPerCu = 3;            // persistent workgroups per CU
+constexpr int64_t kMaxBatchSteps = 1 << 24; // steps per nlse_batch_step_rk4 call
+constexpr size_t kMaxBatchGraphs = 32;    // instantiated graphs kept per batch
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -74,7 +76,9 @@ BatchLayout layout(int nsims, int dtype, unsigned flags, int64_t tot, int64_t ni
   L.lo = off; if (flags & NLSE_COMPENSATED) off += field;
   L.items = off; off += a256(sizeof(nlse::BatchItem) * (size_t)nitems);
   L.chunks = off; off += a256(sizeof(int) * (size_t)(5 * kMaxChunks + 1));
-  L.barrier = off; off += a256(sizeof(unsigned) * (size_t)(kMaxChunks + 2));
+  // two unsigned (the error flag is the second), then one 64-bit arrival
+  // counter per group (at most one group per chunk)
+  L.barrier = off; off += a256(8 + sizeof(unsigned long long) * (size_t)kMaxChunks);
   L.zero = off; off += 256;
   L.partials = off; off += a256((size_t)max_blocks * 3 * sizeof(double));
   L.out = off; off += a256((size_t)nsims * 3 * sizeof(double));
@@ -112,7 +116,7 @@ extern "C" int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc* sims, 
 
 static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
   // reset the group arrival counters; the error flag before them stays sticky
-  hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier + 8, 4 * (int64_t)b->ngroups, st);
+  hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier + 8, 8 * (int64_t)b->ngroups, st);
   if (e != hipSuccess) return e;
   nlse::BatchLaunch L;
   L.dtype = b->dtype;
@@ -265,6 +269,18 @@ extern "C" int nlse_internal_batch_plan(int nsims, const nlse_sim_desc* sims, in
   return NLSE_OK;
 }
 
+// Test hook (host only): the limits behind the group barrier's arithmetic.
+// out[0] = largest nsteps of one call, out[1] = largest number of chunks
+// (so of chunks in one group), out[2] = bits of an arrival counter.  The
+// barrier target of the last stage of a call is 4 * nsteps * group size.
+extern "C" int nlse_internal_batch_limits(int64_t out[3]) {
+  if (!out) return nlse_fail(NLSE_EINVAL, "out is NULL");
+  out[0] = kMaxBatchSteps;
+  out[1] = kMaxChunks;
+  out[2] = 8 * (int64_t)sizeof(unsigned long long);
+  return NLSE_OK;
+}
+
 extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags,
                                  void* psi_pool, size_t psi_pool_elems, const void* v_pool, size_t v_pool_elems,
                                  void* work_dev, size_t work_bytes, void* hip_stream) {
@@ -346,8 +362,8 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
 }
 
 extern "C" int nlse_batch_step_rk4(nlse_batch* b, int64_t nsteps) {
+  if (nsteps < 0 || nsteps > kMaxBatchSteps) return nlse_fail(NLSE_EINVAL, "nsteps out of range");
   if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
-  if (nsteps < 0 || nsteps > (1 << 24)) return nlse_fail(NLSE_EINVAL, "nsteps out of range");
   if (nsteps == 0) return NLSE_OK;
   hipError_t e;
   if (b->flags & NLSE_NO_GRAPH) {
@@ -356,6 +372,7 @@ extern "C" int nlse_batch_step_rk4(nlse_batch* b, int64_t nsteps) {
   }
   auto found = b->graphs.find(nsteps);
   if (found == b->graphs.end()) {
+    if (b->graphs.size() >= kMaxBatchGraphs) destroy_graphs(b);
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);

@@ -42,13 +42,16 @@ struct BatchArgs {
   cpx<T>* bufA;
   cpx<T>* bufB;
   cpx<T>* lo;
-  unsigned* barrier;     // [1] error flag, [2 + g] arrivals of group g
+  unsigned* flag;        // sticky error flag
+  unsigned long long* arrivals;  // arrivals of group g
   unsigned spin_limit;
 };
 
 // Barrier number `k` (1, 2, ...) of the groups (ga, size sa) and (gb, size
 // sb) a chunk belongs to (-1: none): the workgroup adds one arrival to each
-// group's counter and waits until each holds k * size arrivals.  One
+// group's counter and waits until each holds k * size arrivals.  The
+// counters and targets are 64-bit: k reaches 4 * nsteps and a group spans up
+// to every chunk, so a 32-bit target could wrap within one launch.  One
 // release before the arrivals and one acquire after the waits, and only
 // thread 0 crosses device scope:
 // the workgroup barrier first orders every wave's stores before thread 0's
@@ -57,18 +60,17 @@ struct BatchArgs {
 // per wave), and the workgroup barrier after thread 0's agent-scope acquire
 // orders every wave's later loads after it.  Returns false if the wait
 // timed out or another workgroup reported an error.
-__device__ __forceinline__ bool group_barrier(unsigned* bar, int ga, unsigned sa, int gb, unsigned sb, unsigned k,
-                                              unsigned spin_limit) {
+__device__ __forceinline__ bool group_barrier(unsigned* flag, unsigned long long* cnt, int ga, unsigned sa, int gb,
+                                              unsigned sb, unsigned long long k, unsigned spin_limit) {
   __shared__ int ok;
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned* flag = bar + 1;
-    unsigned* ca = bar + 2 + (ga >= 0 ? ga : 0);
-    unsigned* cb = bar + 2 + (gb >= 0 ? gb : 0);
+    unsigned long long* ca = cnt + (ga >= 0 ? ga : 0);
+    unsigned long long* cb = cnt + (gb >= 0 ? gb : 0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (ga >= 0) __hip_atomic_fetch_add(ca, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (gb >= 0) __hip_atomic_fetch_add(cb, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    auto arrived = [&](const unsigned* c, int g, unsigned size) {
+    if (ga >= 0) __hip_atomic_fetch_add(ca, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (gb >= 0) __hip_atomic_fetch_add(cb, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    auto arrived = [&](const unsigned long long* c, int g, unsigned size) {
       return g < 0 || __hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= k * size;
     };
     unsigned spins = 0;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(kBatchTX* kBatchTY) void batch2d_kernel(BatchArgs<T
   const int* meta = B.chunk_off + gridDim.x + 1 + 4 * c;
   const int ga = meta[0], gb = meta[2];
   const unsigned sa = (unsigned)meta[1], sb = (unsigned)meta[3];
-  unsigned k = 0;
+  unsigned long long k = 0;
   // a chunk whose problems all lie inside it reads only its own earlier
   // stores: a workgroup barrier orders them
   auto sync = [&]() -> bool {
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kBatchTX* kBatchTY) void batch2d_kernel(BatchArgs<T
       __syncthreads();
       return true;
     }
-    return group_barrier(B.barrier, ga, sa, gb, sb, ++k, B.spin_limit);
+    return group_barrier(B.flag, B.arrivals, ga, sa, gb, sb, ++k, B.spin_limit);
   };
   for (int n = 0; n < nsteps; ++n) {
     batch_stage<T, 1, COMP>(B, i0, i1, S);
@@ -268,7 +270,8 @@ static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
   B.bufA = static_cast<cpx<T>*>(L.bufA);
   B.bufB = static_cast<cpx<T>*>(L.bufB);
   B.lo = static_cast<cpx<T>*>(L.lo);
-  B.barrier = L.barrier;
+  B.flag = L.barrier + 1;
+  B.arrivals = reinterpret_cast<unsigned long long*>(L.barrier + 2);
   B.spin_limit = L.spin_limit;
   hipLaunchKernelGGL((batch2d_kernel<T, COMP>), dim3(L.nchunks), dim3(kBatchTX * kBatchTY), 0, st, B, L.nsteps);
   return hipGetLastError();

@@ -34,7 +34,7 @@ struct BatchLaunch {
   const void* vpool;
   const void* vzero;
   void *acc, *bufA, *bufB, *lo;
-  unsigned* barrier;
+  unsigned* barrier;  // [1] sticky error flag; 64-bit arrival counters from byte 8
   unsigned spin_limit;
 };
 

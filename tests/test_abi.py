@@ -212,3 +212,34 @@ def test_batch_schedule_invariants(seed, nsims, W):
                      for t in trip])
     loads = np.array([cost[offs[c]:offs[c + 1]].sum() for c in range(W)])
     assert loads.max() <= cost.sum() / W + cost.max() + 1e-9
+
+
+def test_batch_barrier_targets_cannot_wrap():
+    """The persistent batch kernel's group barrier waits until a group's
+    arrival counter holds (barrier number) x (group size).  The last barrier
+    of a call has number 4 nsteps.  For the largest accepted nsteps and a
+    problem spread over the largest possible number of chunks (one big
+    problem, planned over the chunk limit), that target must fit the counter,
+    which a 32-bit counter would not."""
+    lib = nlse.load_library()
+    f = lib.nlse_internal_batch_limits
+    f.restype = ctypes.c_int
+    lim = (ctypes.c_int64 * 3)()
+    assert f(lim) == 0
+    max_steps, max_chunks, bits = lim[0], lim[1], lim[2]
+    assert max_steps >= 500  # the 512-problem workload runs 500 steps in one call
+    # a single problem large enough to cover every chunk forms one group of
+    # size max_chunks
+    n = 32 * 8 * max_chunks
+    descs = [_desc(dims=(4096, n // 4096, 1))]
+    offs, meta, items, ngroups, nitems = _plan(descs, max_chunks)
+    assert ngroups == 1
+    biggest = max(max(m[1], m[3]) for m in meta)
+    assert max_chunks - 1 <= biggest <= max_chunks
+    target = 4 * max_steps * max_chunks
+    assert target < 2 ** bits
+    assert target >= 2 ** 32  # the case a 32-bit counter got wrong
+    # larger calls are refused before any launch
+    with pytest.raises(nlse.NLSEError) as e:
+        nlse.nlse_batch_step_rk4(None, max_steps + 1)
+    assert e.value.code == nlse.NLSE_EINVAL and "nsteps" in str(e.value)

@@ -394,31 +394,45 @@ def _golden_case(name, problem, dtype, compensated, autotune=True):
 
 
 @pytest.mark.parametrize("compensated", [True, False])
-def test_c2_vortex_1000_steps_vs_oracle(compensated):
-    """1024^2, FP32 2SHOC + MSD, 1000 steps, sampled against the FP64 oracle:
-    both FP32 modes within 1e-5 relative L2 after 1000 steps."""
-    err, M, E, G = _golden_case("c2_vortex2d_1024x1024_1000", wl.vortex2d(n=1024, nsteps=1000), "f32", compensated)
-    print(f"c2 1000 steps compensated={compensated}: sampled rel L2 {err:.3e}")
-    assert err < TOL["f32"]
-    assert M == pytest.approx(float(G["mass"]), rel=1e-5)
-    assert E == pytest.approx(float(G["energy"]), rel=1e-4)
+def test_c2_vortex_1000_and_2000_steps_vs_oracle(compensated):
+    """1024^2, FP32 2SHOC + MSD, sampled against the FP64 oracle after 1000
+    and (same run continued) 2000 steps.
 
-
-# Plain FP32 stores psi in FP32 after every stage, so its error grows like a
-# random walk of roundings, with the square root of the step count; the
-# 1e-5 bound at 1000 steps becomes 1e-5 * sqrt(2) at 2000.  The compensated
-# mode keeps psi in FP32 + FP32 (accumulated in FP64) and stays within 1e-5.
-C2_2000_TOL = {True: TOL["f32"], False: TOL["f32"] * np.sqrt(2.0)}
-
-
-@pytest.mark.parametrize("compensated", [True, False])
-def test_c2_vortex_2000_steps_vs_oracle(compensated):
-    """1024^2, FP32 2SHOC + MSD, 2000 steps, sampled against the FP64 oracle."""
-    err, M, E, G = _golden_case("c2_vortex2d_1024x1024_2000", wl.vortex2d(n=1024), "f32", compensated)
-    print(f"c2 2000 steps compensated={compensated}: sampled rel L2 {err:.3e}")
-    assert err < C2_2000_TOL[compensated]
-    assert M == pytest.approx(float(G["mass"]), rel=1e-5)
-    assert E == pytest.approx(float(G["energy"]), rel=1e-4)
+    The bar, 1e-5 relative L2, is stated after 1000 steps; both FP32 modes
+    meet it there.  At 2000 steps the compensated mode still meets it.  Plain
+    FP32 rounds psi to FP32 after every stage, so its error keeps growing;
+    the test records how: independent roundings add up like a random walk,
+    a factor sqrt(2) from 1000 to 2000 steps, and the measured ratio must lie
+    between 1 and 1.8 (sqrt 2 = 1.41, 2 would be linear growth).  It is not
+    held to 1e-5 at 2000 steps (measured 1.00e-5)."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev
+    p = wl.vortex2d(n=1024, nsteps=2000)
+    G1, G2 = _golden("c2_vortex2d_1024x1024_1000"), _golden("c2_vortex2d_1024x1024_2000")
+    dt = p.dt_fraction * oracle.dt_max(p.ndim, p.order, p.h, p.a)
+    assert dt == float(G1["dt"]) == float(G2["dt"])
+    psi = to_dev(p.psi0, "f32")
+    g = Grid(psi, p.h, p.a, p.s, compensated=compensated)
+    g.autotune(p.order, p.bc, dt)
+    errs, me = [], []
+    for G in (G1, G2):
+        g.step(dt, 1000, order=p.order, bc=p.bc)
+        torch.cuda.synchronize()
+        flat = psi.cpu().numpy().astype(np.complex128).reshape(-1)
+        errs.append(rel_l2(flat[G["idx"]], G["val"]))
+        me.append(g.mass_energy(p.order, p.bc))
+    g.close()
+    print(f"c2 compensated={compensated}: sampled rel L2 {errs[0]:.3e} (1000 steps), "
+          f"{errs[1]:.3e} (2000 steps), ratio {errs[1] / errs[0]:.3f}")
+    assert errs[0] < TOL["f32"]
+    if compensated:
+        assert errs[1] < TOL["f32"]
+    else:
+        assert 1.0 < errs[1] / errs[0] < 1.8
+    for (M, E), G in zip(me, (G1, G2)):
+        assert M == pytest.approx(float(G["mass"]), rel=1e-5)
+        assert E == pytest.approx(float(G["energy"]), rel=1e-4)
 
 
 def test_c2_vortex_fp64_check():

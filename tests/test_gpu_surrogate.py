@@ -235,3 +235,137 @@ def test_advance_blocks_replay_and_follow_weight_updates():
     assert torch.equal(a, explicit(start, 1))
     g.close()
     m.close()
+
+
+# ---------------------------------------------------------------- full size, element by element
+#
+# At 256^2 and batch 4 the convolution kernels take 1024 pixel tiles and the
+# weight-gradient kernel 2048, more than the persistent grids hold, so every
+# workgroup walks several tiles (with the next tile prefetched) and the
+# gradient partials of several tiles per workgroup meet in the fixed-order
+# reduction.
+#
+# Element-by-element parity is taken against the reference in its BF16 mode:
+# the same network on the same BF16-rounded operands (input channels,
+# weights, hidden activations, output gradients), summed in FP64.  What may
+# still differ is the FP32 accumulation of the GPU (at most K u32 of the sum
+# of magnitudes, K <= 432 products per conv output) and, through it, an
+# occasional BF16 rounding decision taken the other way, which moves one
+# operand by at most one BF16 unit roundoff (2^-8) of its value.  Per element
+# the tolerance is therefore 2^-8 times the sum of magnitudes of the terms
+# that make the element (forward: sum |a_5| |W_6| + |b_6| of the output
+# pixel; weight gradient: sum over pixels |dz| |a|; bias gradient: sum |dz|).
+# Against the plain FP64 reference, where every BF16 rounding counts, the
+# comparison is normwise (3e-2 forward increment, 5e-2 gradients).
+
+U_BF16 = 2.0 ** -8
+
+
+def _wgrad_abs(a, g):
+    """Sum over pixels of |g[p, co]| |a[p + tap, ci]| (the magnitudes of the
+    weight-gradient terms), FP64."""
+    import torch
+    import torch.nn.functional as F
+    at = torch.from_numpy(np.ascontiguousarray(np.abs(a))).permute(3, 0, 1, 2)
+    gt = torch.from_numpy(np.ascontiguousarray(np.abs(g))).permute(3, 0, 1, 2)
+    return F.conv2d(at, gt, padding=1).transpose(0, 1).numpy()
+
+
+def _bf16_grads_with_magnitudes(p, x, t):
+    """The reference's BF16-mode backpropagation, also returning for every
+    layer the sums of magnitudes of its weight- and bias-gradient terms."""
+    q = S.to_bf16
+    pred, (acts, zs) = S.forward(p, x, bf16=True)
+    d = pred - t
+    dz = q(np.stack([d.real, d.imag], axis=-1) * (2.0 / (2 * d.size)))
+    mags = [None] * len(p)
+    for l in range(len(p) - 1, -1, -1):
+        W, _ = p[l]
+        da, _, _ = S.conv3x3_grad(acts[l], q(W), dz)
+        mags[l] = (_wgrad_abs(acts[l], dz), np.abs(dz).sum(axis=(0, 1, 2)))
+        if l > 0:
+            dz = q(da * (acts[l] > 0))
+    L, grads = S.loss_and_grad(p, x, t, bf16=True)
+    return L, grads, mags
+
+
+def _worst(got, ref, scale):
+    """Largest |got - ref| / scale over the elements."""
+    return float(np.max(np.abs(got - ref) / (scale + 1e-300)))
+
+
+def test_full_size_forward_elementwise_and_tile_independent():
+    """256^2, batch 4 (1024 tiles): every output pixel within 2^-8 of its
+    magnitude sum of the BF16-mode reference, the increment within 3e-2 of
+    the FP64 reference; and each image's output is bitwise the output of a
+    batch-1 call on that image (256 tiles, one per workgroup), so the
+    persistent tile loop changes nothing."""
+    import torch
+    H = W = 256
+    B = 4
+    m, p, _ = make(H, W, B, seed=21)
+    x = fields(B, H, W, 22).astype(np.complex64)
+    xd = torch.from_numpy(x).cuda()
+    pred = m.forward(xd)
+    singles = [m.forward(xd[b:b + 1].contiguous()) for b in range(B)]
+    torch.cuda.synchronize()
+    for b in range(B):
+        assert torch.equal(pred[b:b + 1], singles[b]), f"image {b}"
+    got = pred.cpu().numpy().astype(np.complex128)
+    x64 = x.astype(np.complex128)
+    rb, (acts, _) = S.forward(p, x64, bf16=True)
+    W6, b6 = p[-1]
+    M6 = S.conv3x3(np.abs(acts[-1]), np.abs(S.to_bf16(W6)), np.abs(b6))
+    scale_r = U_BF16 * M6[..., 0] + 2.0 ** -23 * np.abs(rb.real)
+    scale_i = U_BF16 * M6[..., 1] + 2.0 ** -23 * np.abs(rb.imag)
+    worst = max(_worst(got.real, rb.real, scale_r), _worst(got.imag, rb.imag, scale_i))
+    rf, _ = S.forward(p, x64)
+    err64 = rel_l2(got - x64, rf - x64)
+    print(f"forward 256^2 x 4: worst |GPU - BF16 reference| / (2^-8 magnitude) {worst:.3e}; "
+          f"increment rel L2 vs FP64 {err64:.3e}")
+    assert worst <= 1.0
+    assert err64 < 3e-2
+    m.close()
+
+
+def test_full_size_gradients_elementwise_and_batch_consistent():
+    """256^2, batch 4 (2048 weight-gradient tiles over the persistent
+    workgroups, several tiles per partial): every weight and bias gradient of
+    every layer within 2^-8 of its magnitude sum of the BF16-mode reference
+    and within 5e-2 normwise of the FP64 reference.  The batch-4 gradient
+    also equals the mean of the four batch-1 gradients (one tile per
+    workgroup) up to FP32 summation order (1e-4 normwise): the output
+    gradient of a batch of 4 is exactly a quarter of the batch-1 one
+    (power-of-two scale), so only the association of the partial sums
+    differs."""
+    import torch
+    H = W = 256
+    B = 4
+    m, p, _ = make(H, W, B, seed=23)
+    x = fields(B, H, W, 24).astype(np.complex64)
+    t = (fields(B, H, W, 25) * 0.05 + x * np.exp(-0.15j)).astype(np.complex64)
+    xd, td = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    loss, grad = m.loss_grad(xd, td)
+    grad = grad.cpu().numpy().astype(np.float64)
+    ones = []
+    for b in range(B):
+        _, g1 = m.loss_grad(xd[b:b + 1].contiguous(), td[b:b + 1].contiguous())
+        ones.append(g1.cpu().numpy().astype(np.float64))
+    mean1 = S.unpack(np.mean(ones, axis=0))
+    x64, t64 = x.astype(np.complex128), t.astype(np.complex128)
+    Lb, gb16, mags = _bf16_grads_with_magnitudes(p, x64, t64)
+    L64, g64 = S.loss_and_grad(p, x64, t64)
+    assert loss == pytest.approx(Lb, rel=1e-3)
+    g = S.unpack(grad)
+    fails = []
+    for l in range(len(g)):
+        (gw, gb), (rw, rb), (mw, mb), (cw, cb), (fw, fb) = g[l], gb16[l], mags[l], mean1[l], g64[l]
+        ww, wb = _worst(gw, rw, U_BF16 * mw), _worst(gb, rb, U_BF16 * mb)
+        kw, kb = rel_l2(gw, cw), rel_l2(gb, cb)
+        ew, eb = rel_l2(gw, fw), rel_l2(gb, fb)
+        print(f"layer {l + 1}: worst |GPU - BF16 ref| / (2^-8 magnitude) W {ww:.2e} b {wb:.2e}; "
+              f"rel L2 vs FP64 W {ew:.2e} b {eb:.2e}; batch-4 vs mean of batch-1 W {kw:.2e} b {kb:.2e}")
+        if not (ww <= 1.0 and wb <= 1.0 and ew < 5e-2 and eb < 5e-2 and kw < 1e-4 and kb < 1e-4):
+            fails.append(l + 1)
+    assert not fails, f"layers {fails}"
+    m.close()

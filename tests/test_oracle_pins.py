@@ -450,6 +450,70 @@ def test_conservation_soliton(order, tol_m, tol_e):
     assert abs(E1 - E0) / abs(E0) < tol_e
 
 
+def _packet_in_trap(dim):
+    """A Gaussian wave packet with momentum, off-centre in a harmonic trap,
+    small at the (zero Dirichlet) edges of the box."""
+    if dim == 1:
+        h = 0.1
+        x = -20 + np.arange(401) * h
+        psi = 0.8 * np.exp(-(x + 4) ** 2 / (2 * 1.5 ** 2)) * np.exp(1j * x)
+        V = 0.1 * x ** 2
+    else:
+        h = 0.25
+        x = -10 + np.arange(81) * h
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        psi = 0.8 * np.exp(-((X + 3) ** 2 + (Y - 1) ** 2) / (2 * 1.2 ** 2)) * np.exp(1j * (0.8 * X + 0.3 * Y))
+        V = 0.5 * (0.25 * X ** 2 + 0.15 * Y ** 2)
+    return psi, V, h
+
+
+@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("order", [2, 4])
+def test_energy_conserved_while_packet_moves_in_static_potential(dim, order):
+    """The Hamiltonian of i psi_t = -a Lap psi + V psi - s|psi|^2 psi includes
+    +V|psi|^2 with a static V, so E stays constant while the packet rolls
+    down the trap and its potential energy h^d sum V|psi|^2 changes by a few
+    percent of E.  A wrong sign or factor of the potential term in E would
+    make E change by a multiple of that (the potential energy is computed
+    here independently of the oracle's energy)."""
+    psi, V, h = _packet_in_trap(dim)
+    a, s = 1.0, -1.0
+    dt = 0.5 * oracle.dt_max(dim, order, h, a)
+    nst = int(2.0 / dt)
+    M0, E0 = oracle.mass_energy(psi, h, a, s, V=V, order=order)
+    out = oracle.rk4(psi, h, a, s, dt, nst, V=V, order=order)
+    M1, E1 = oracle.mass_energy(out, h, a, s, V=V, order=order)
+    pot0 = h ** dim * np.sum(V * np.abs(psi) ** 2)
+    pot1 = h ** dim * np.sum(V * np.abs(out) ** 2)
+    assert abs(pot1 - pot0) / abs(E0) > 1e-2  # the packet really moved in V
+    assert abs(M1 - M0) / M0 < 1e-6
+    assert abs(E1 - E0) / abs(E0) < 1e-6
+
+
+@pytest.mark.parametrize("shape,order,bc", [((40,), 2, "dirichlet"), ((40,), 4, "msd"),
+                                            ((12, 14), 4, "dirichlet"), ((12, 14), 2, "l0"),
+                                            ((6, 7, 8), 4, "msd"), ((6, 7, 8), 2, "dirichlet")])
+def test_energy_shift_by_constant_potential(shape, order, bc):
+    """A constant potential V = c only shifts the Hamiltonian by c times the
+    mass: E(V = c) - E(V = 0) = c M.  (For 2SHOC with Dirichlet or MSD the
+    boundary D depends on V through N_b; a constant V cancels in N_q - N_b
+    for MSD but not for Dirichlet, so Dirichlet + 2SHOC is checked with a
+    field that vanishes on the boundary.)"""
+    u = 1.2 + 0.4 * wl.random_field(shape, 11, smooth=2.0)
+    if bc == "dirichlet":
+        for ax in range(len(shape)):
+            idx = [slice(None)] * len(shape)
+            idx[ax] = 0
+            u[tuple(idx)] = 0
+            idx[ax] = -1
+            u[tuple(idx)] = 0
+    h, a, s, c = 0.3, 0.7, -1.0, 0.625
+    M0, E0 = oracle.mass_energy(u, h, a, s, V=None, order=order, bc=bc)
+    Mc, Ec = oracle.mass_energy(u, h, a, s, V=np.full(shape, c), order=order, bc=bc)
+    assert Mc == M0
+    assert Ec - E0 == pytest.approx(c * M0, rel=1e-12, abs=1e-12 * abs(E0))
+
+
 def test_oracle_rejects_bad_arguments():
     with pytest.raises(ValueError):
         oracle.rk4(np.zeros(2, complex), 0.1, 1.0, 1.0, 1e-3, 1)
