@@ -16,6 +16,8 @@ import oracle
 from oracle import surrogate as S
 from paper_1203_1263_amd import workloads as wl
 from gpu_util import rel_l2
+from surrogate_criteria import (SURROGATE_CRITERIA, bf16_forward_with_scale, bf16_grads_with_scales,
+                                worst_ratio)
 
 pytestmark = pytest.mark.gpu
 
@@ -245,58 +247,35 @@ def test_advance_blocks_replay_and_follow_weight_updates():
 # gradient partials of several tiles per workgroup meet in the fixed-order
 # reduction.
 #
-# Element-by-element parity is taken against the reference in its BF16 mode:
-# the same network on the same BF16-rounded operands (input channels,
-# weights, hidden activations, output gradients), summed in FP64.  What may
-# still differ is the FP32 accumulation of the GPU (at most K u32 of the sum
-# of magnitudes, K <= 432 products per conv output) and, through it, an
-# occasional BF16 rounding decision taken the other way, which moves one
-# operand by at most one BF16 unit roundoff (2^-8) of its value.  Per element
-# the tolerance is therefore 2^-8 times the sum of magnitudes of the terms
-# that make the element (forward: sum |a_5| |W_6| + |b_6| of the output
-# pixel; weight gradient: sum over pixels |dz| |a|; bias gradient: sum |dz|).
+# Parity is taken against the reference in its BF16 mode: the same network
+# on the same BF16-rounded operands (input channels, weights, hidden
+# activations, output gradients), summed in FP64.  What may differ is the FP32
+# accumulation of the GPU and, through it, a BF16 rounding decision taken the
+# other way, which moves that value by one BF16 unit in the last place (at
+# most 2u of it, u = 2^-8), or a ReLU decision of a pre-activation within
+# FP32 rounding of 0.  Criteria (tests/surrogate_criteria.py; a CPU test
+# checks them on an FP32 emulation of the GPU's roundings and on planted
+# mistakes):
+#   * forward, element by element: an output pixel may differ by the last
+#     layer's terms with their activations moved by one ulp plus the FP32
+#     band of their pre-activation (g(K) times its sum of magnitudes), plus
+#     its own FP32 band and output rounding;
+#   * gradients, element by element: a term dz[p, co] a[p + tap, ci] may
+#     differ through a (as in the forward pass), through dz by one ulp, and
+#     where the ReLU of dz's pre-activation is undecided by the whole
+#     back-propagated value.  Differences propagated from the layers above
+#     enter through dz[., co], which every element of output channel co
+#     shares, so each weight-gradient element is held to the largest such
+#     first-order bound of its output channel;
+#   * normwise, per layer: relative L2 distance to the BF16-mode reference at
+#     most 2e-3 (the FP32 emulation lands at 1e-4 to 5e-4).
 # Against the plain FP64 reference, where every BF16 rounding counts, the
 # comparison is normwise (3e-2 forward increment, 5e-2 gradients).
 
-U_BF16 = 2.0 ** -8
-
-
-def _wgrad_abs(a, g):
-    """Sum over pixels of |g[p, co]| |a[p + tap, ci]| (the magnitudes of the
-    weight-gradient terms), FP64."""
-    import torch
-    import torch.nn.functional as F
-    at = torch.from_numpy(np.ascontiguousarray(np.abs(a))).permute(3, 0, 1, 2)
-    gt = torch.from_numpy(np.ascontiguousarray(np.abs(g))).permute(3, 0, 1, 2)
-    return F.conv2d(at, gt, padding=1).transpose(0, 1).numpy()
-
-
-def _bf16_grads_with_magnitudes(p, x, t):
-    """The reference's BF16-mode backpropagation, also returning for every
-    layer the sums of magnitudes of its weight- and bias-gradient terms."""
-    q = S.to_bf16
-    pred, (acts, zs) = S.forward(p, x, bf16=True)
-    d = pred - t
-    dz = q(np.stack([d.real, d.imag], axis=-1) * (2.0 / (2 * d.size)))
-    mags = [None] * len(p)
-    for l in range(len(p) - 1, -1, -1):
-        W, _ = p[l]
-        da, _, _ = S.conv3x3_grad(acts[l], q(W), dz)
-        mags[l] = (_wgrad_abs(acts[l], dz), np.abs(dz).sum(axis=(0, 1, 2)))
-        if l > 0:
-            dz = q(da * (acts[l] > 0))
-    L, grads = S.loss_and_grad(p, x, t, bf16=True)
-    return L, grads, mags
-
-
-def _worst(got, ref, scale):
-    """Largest |got - ref| / scale over the elements."""
-    return float(np.max(np.abs(got - ref) / (scale + 1e-300)))
-
-
 def test_full_size_forward_elementwise_and_tile_independent():
-    """256^2, batch 4 (1024 tiles): every output pixel within 2^-8 of its
-    magnitude sum of the BF16-mode reference, the increment within 3e-2 of
+    """256^2, batch 4 (1024 tiles): every output pixel within its
+    first-order bound of the BF16-mode reference (and the increment within
+    2e-3 of it normwise), the increment within 3e-2 of
     the FP64 reference; and each image's output is bitwise the output of a
     batch-1 call on that image (256 tiles, one per workgroup), so the
     persistent tile loop changes nothing."""
@@ -313,17 +292,15 @@ def test_full_size_forward_elementwise_and_tile_independent():
         assert torch.equal(pred[b:b + 1], singles[b]), f"image {b}"
     got = pred.cpu().numpy().astype(np.complex128)
     x64 = x.astype(np.complex128)
-    rb, (acts, _) = S.forward(p, x64, bf16=True)
-    W6, b6 = p[-1]
-    M6 = S.conv3x3(np.abs(acts[-1]), np.abs(S.to_bf16(W6)), np.abs(b6))
-    scale_r = U_BF16 * M6[..., 0] + 2.0 ** -23 * np.abs(rb.real)
-    scale_i = U_BF16 * M6[..., 1] + 2.0 ** -23 * np.abs(rb.imag)
-    worst = max(_worst(got.real, rb.real, scale_r), _worst(got.imag, rb.imag, scale_i))
+    rb, (sr, si) = bf16_forward_with_scale(p, x64)
+    worst = max(worst_ratio(got.real, rb.real, sr), worst_ratio(got.imag, rb.imag, si))
+    err16 = rel_l2(got - x64, rb - x64)
     rf, _ = S.forward(p, x64)
     err64 = rel_l2(got - x64, rf - x64)
-    print(f"forward 256^2 x 4: worst |GPU - BF16 reference| / (2^-8 magnitude) {worst:.3e}; "
-          f"increment rel L2 vs FP64 {err64:.3e}")
+    print(f"forward 256^2 x 4: worst |GPU - BF16 reference| / bound {worst:.3e}; "
+          f"increment rel L2 vs BF16 reference {err16:.3e}, vs FP64 {err64:.3e}")
     assert worst <= 1.0
+    assert err16 < SURROGATE_CRITERIA["bf16_norm"]
     assert err64 < 3e-2
     m.close()
 
@@ -331,7 +308,8 @@ def test_full_size_forward_elementwise_and_tile_independent():
 def test_full_size_gradients_elementwise_and_batch_consistent():
     """256^2, batch 4 (2048 weight-gradient tiles over the persistent
     workgroups, several tiles per partial): every weight and bias gradient of
-    every layer within 2^-8 of its magnitude sum of the BF16-mode reference
+    every layer within its first-order bound of the BF16-mode reference,
+    each layer within 2e-3 of it normwise,
     and within 5e-2 normwise of the FP64 reference.  The batch-4 gradient
     also equals the mean of the four batch-1 gradients (one tile per
     workgroup) up to FP32 summation order (1e-4 normwise): the output
@@ -353,19 +331,23 @@ def test_full_size_gradients_elementwise_and_batch_consistent():
         ones.append(g1.cpu().numpy().astype(np.float64))
     mean1 = S.unpack(np.mean(ones, axis=0))
     x64, t64 = x.astype(np.complex128), t.astype(np.complex128)
-    Lb, gb16, mags = _bf16_grads_with_magnitudes(p, x64, t64)
+    Lb, gb16, scales = bf16_grads_with_scales(p, x64, t64)
     L64, g64 = S.loss_and_grad(p, x64, t64)
     assert loss == pytest.approx(Lb, rel=1e-3)
     g = S.unpack(grad)
     fails = []
     for l in range(len(g)):
-        (gw, gb), (rw, rb), (mw, mb), (cw, cb), (fw, fb) = g[l], gb16[l], mags[l], mean1[l], g64[l]
-        ww, wb = _worst(gw, rw, U_BF16 * mw), _worst(gb, rb, U_BF16 * mb)
+        (gw, gb), (rw, rb), (mw, mb), (cw, cb), (fw, fb) = g[l], gb16[l], scales[l], mean1[l], g64[l]
+        ww, wb = worst_ratio(gw, rw, mw), worst_ratio(gb, rb, mb)
+        nw, nb = rel_l2(gw, rw), rel_l2(gb, rb)
         kw, kb = rel_l2(gw, cw), rel_l2(gb, cb)
         ew, eb = rel_l2(gw, fw), rel_l2(gb, fb)
-        print(f"layer {l + 1}: worst |GPU - BF16 ref| / (2^-8 magnitude) W {ww:.2e} b {wb:.2e}; "
-              f"rel L2 vs FP64 W {ew:.2e} b {eb:.2e}; batch-4 vs mean of batch-1 W {kw:.2e} b {kb:.2e}")
-        if not (ww <= 1.0 and wb <= 1.0 and ew < 5e-2 and eb < 5e-2 and kw < 1e-4 and kb < 1e-4):
+        print(f"layer {l + 1}: worst |GPU - BF16 ref| / bound W {ww:.2e} b {wb:.2e}; "
+              f"rel L2 vs BF16 ref W {nw:.2e} b {nb:.2e}; vs FP64 W {ew:.2e} b {eb:.2e}; "
+              f"batch-4 vs mean of batch-1 W {kw:.2e} b {kb:.2e}")
+        lim = SURROGATE_CRITERIA["bf16_norm"]
+        if not (ww <= 1.0 and wb <= 1.0 and nw < lim and nb < lim and ew < 5e-2 and eb < 5e-2
+                and kw < 1e-4 and kb < 1e-4):
             fails.append(l + 1)
     assert not fails, f"layers {fails}"
     m.close()
