@@ -95,6 +95,9 @@ def bench_batch(args):
     probs = wl.batch2d()
     dts = [0.8 * nlse_dt_max(2, p.order, p.h, p.a) for p in probs]
     b = Batch(probs, dts, compensated=not args.plain)
+    t_tune = time.perf_counter()
+    b.autotune()  # tile and workgroups per CU for this batch (fields untouched)
+    t_tune = time.perf_counter() - t_tune
     b.step(args.steps)  # capture + warm-up with the timed step count
     b.status()
     stream = torch.cuda.current_stream()
@@ -118,7 +121,9 @@ def bench_batch(args):
            "vs_baseline": None, "dtype": "f32" + ("" if args.plain else "+f64-compensated"),
            "data": "synthetic",
            "config": {"workload": "batch2d_512_problems_persistent_graph", "points": npts,
-                      "workgroups": info["workgroups"], "items": info["items"]},
+                      "workgroups": info["workgroups"], "items": info["items"],
+                      "tile": list(b.config()[:2]), "wg_per_cu": b.config()[2], "autotuned": True,
+                      "autotune_s": t_tune},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                         "kernel": "batch2d_kernel (persistent, all stages)", "bytes_per_point_step": bpp}}

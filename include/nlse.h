@@ -198,8 +198,8 @@ int nlse_destroy_grid(nlse_grid *g);
  * once into a HIP graph per step count and replayed).  Every problem follows
  * exactly the single-grid integrator above (same scheme, boundary forms and
  * RK4 stages, Eq. RK4 / Eq. RK4_GPU) with its own a, s, V, h, dt, order and
- * bc; a problem gives bitwise the same result alone (tile 32x8) as inside a
- * batch.  Only 2D problems are supported (NLSE_EUNSUPPORTED otherwise). */
+ * bc; a problem gives bitwise the same result alone (with the batch's
+ * tile) as inside a batch.  Only 2D problems are supported (NLSE_EUNSUPPORTED otherwise). */
 typedef struct {
     int ndim;            /* must be 2                                       */
     int64_t dims[3];     /* {Nx, Ny, 1}, Nx, Ny >= 3                        */
@@ -221,8 +221,9 @@ int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc *sims, int dtype,
  * device pools; each problem's field must lie inside psi_pool and fields must
  * not overlap (not checked).  work_dev: >= nlse_batch_workspace_bytes bytes,
  * 256-byte aligned, borrowed.  flags: NLSE_COMPENSATED (FP32), NLSE_NO_GRAPH.
- * Builds a cost-balanced static schedule of (problem, 32x8 tile) items over
- * as many workgroups as the device holds at once; synchronises the stream. */
+ * Builds a cost-balanced static schedule of (problem, tile) items over the
+ * persistent workgroups (tile 32x8, 3 per CU until reconfigured, see
+ * nlse_batch_set_config); synchronises the stream. */
 int nlse_batch_create(nlse_batch **b, int nsims, const nlse_sim_desc *sims,
                       int dtype, unsigned flags, void *psi_pool,
                       size_t psi_pool_elems, const void *v_pool,
@@ -246,6 +247,22 @@ int nlse_batch_mass_energy(nlse_batch *b, double *mass, double *energy);
 /* Synchronises; NLSE_EDEVICE if a barrier of the persistent kernel timed
  * out since creation (the fields are then not valid), else NLSE_OK. */
 int nlse_batch_status(nlse_batch *b);
+
+/* Tile (tx x ty: 32x8, 64x4 or 64x8) and persistent workgroups per CU
+ * (1..16; the grid holds min(wg_per_cu, what fits on a CU) x CUs
+ * workgroups) of the batched kernel.  Any configuration gives bitwise the
+ * same fields as single grids with that tile.  nlse_batch_set_config
+ * rebuilds the static schedule for it (synchronises; NLSE_EUNSUPPORTED for
+ * a tile that is not compiled).  Created batches use 32x8 and 3 per CU.
+ * nlse_batch_autotune times every tile with 2..5 workgroups per CU (up to
+ * what fits) on this batch, running RK4 stages 1-3 only so the fields and
+ * the compensation term are not changed, keeps the fastest and stores it in
+ * the cache file named by $NLSE_TUNE_CACHE if set (a cached choice for the
+ * same problem shapes, schemes and boundary conditions is reused without
+ * timing).  cfg = {tx, ty, wg_per_cu}. */
+int nlse_batch_set_config(nlse_batch *b, int tx, int ty, int wg_per_cu);
+int nlse_batch_get_config(const nlse_batch *b, int cfg[3]);
+int nlse_batch_autotune(nlse_batch *b);
 
 /* info[0..3] = workgroups of the persistent launch, work items, total grid
  * points, captured graphs. */

@@ -672,7 +672,7 @@ static std::string cache_key(const nlse_grid* g, int order, int bc) {
   return buf;
 }
 
-static bool cache_lookup(const std::string& key, int t[3]) {
+bool nlse_cache_lookup(const std::string& key, int t[3]) {
   const char* path = getenv("NLSE_TUNE_CACHE");
   if (!path || !*path) return false;
   FILE* f = fopen(path, "r");
@@ -689,7 +689,7 @@ static bool cache_lookup(const std::string& key, int t[3]) {
   return found;
 }
 
-static void cache_store(const std::string& key, const int t[3], float ms) {
+void nlse_cache_store(const std::string& key, const int t[3], float ms) {
   const char* path = getenv("NLSE_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
@@ -708,7 +708,7 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
   const std::string key = cache_key(g, order, bc);
   int cached[3];
-  if (cache_lookup(key, cached) && tile_fits(g, order, cached)) {
+  if (nlse_cache_lookup(key, cached) && tile_fits(g, order, cached)) {
     memcpy(g->tile[tile_slot(order)], cached, sizeof cached);
     return NLSE_OK;
   }
@@ -782,6 +782,6 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "autotune launch");
   memcpy(g->tile[tile_slot(order)], best_t.data(), 3 * sizeof(int));
-  cache_store(key, best_t.data(), best / reps);
+  nlse_cache_store(key, best_t.data(), best / reps);
   return NLSE_OK;
 }

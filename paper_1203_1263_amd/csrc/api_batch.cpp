@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -20,7 +21,8 @@ namespace {
 
 constexpr int kMaxChunks = 8192;          // upper bound of persistent workgroups
 constexpr unsigned kSpinLimit = 1u << 25; // bounded barrier wait (~1-2 s)
-constexpr int kMaxWgPerCu = 3;            // persistent workgroups per CU
+constexpr int kDefaultWgPerCu = 3;        // persistent workgroups per CU (untuned)
+constexpr int kMinWgPerCu = 2, kMaxWgPerCu = 5;  // the autotuner's range
 constexpr int64_t kMaxBatchSteps = 1 << 24; // steps per nlse_batch_step_rk4 call
 constexpr size_t kMaxBatchGraphs = 32;    // instantiated graphs kept per batch
 
@@ -30,6 +32,19 @@ struct BatchLayout {
   size_t acc, bufA, bufB, lo, items, chunks, barrier, zero, partials, out, total;
 };
 
+// Work items of a problem with tile tx x ty.
+int64_t tiles_of(const nlse_sim_desc& d, int tx, int ty) {
+  return ((d.dims[0] + tx - 1) / tx) * ((d.dims[1] + ty - 1) / ty);
+}
+
+bool tile_compiled(int tx, int ty) {
+  for (const auto& t : nlse::kBatchTiles)
+    if (t[0] == tx && t[1] == ty) return true;
+  return false;
+}
+
+// *nitems: work items of the tile that makes the most (the workspace holds
+// the descriptors of any compiled tile).
 int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, int64_t* total_pts,
              int64_t* nitems, int64_t* max_blocks) {
   if (nsims < 1) return nlse_fail(NLSE_EINVAL, "nsims must be >= 1");
@@ -38,7 +53,8 @@ int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, in
   if (flags & ~(NLSE_COMPENSATED | NLSE_NO_GRAPH)) return nlse_fail(NLSE_EINVAL, "unknown flag bits");
   if ((flags & NLSE_COMPENSATED) && dtype != NLSE_F32)
     return nlse_fail(NLSE_EUNSUPPORTED, "NLSE_COMPENSATED applies to FP32 only");
-  int64_t tot = 0, items = 0, mb = 1;
+  int64_t tot = 0, mb = 1;
+  int64_t items_t[3] = {0, 0, 0};
   for (int j = 0; j < nsims; ++j) {
     const nlse_sim_desc& d = sims[j];
     if (d.ndim != 2) return nlse_fail(NLSE_EUNSUPPORTED, "problem %d: batches hold 2D problems only", j);
@@ -55,9 +71,10 @@ int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, in
     if (d.psi_offset < 0 || d.v_offset < -1) return nlse_fail(NLSE_EINVAL, "problem %d: bad offsets", j);
     const int64_t n = d.dims[0] * d.dims[1];
     tot += n;
-    items += ((d.dims[0] + nlse::kBatchTX - 1) / nlse::kBatchTX) * ((d.dims[1] + nlse::kBatchTY - 1) / nlse::kBatchTY);
+    for (int k = 0; k < 3; ++k) items_t[k] += tiles_of(d, nlse::kBatchTiles[k][0], nlse::kBatchTiles[k][1]);
     mb = std::max(mb, nlse::reduce_blocks(n));
   }
+  const int64_t items = std::max({items_t[0], items_t[1], items_t[2]});
   if (items > ((int64_t)1 << 31) - 1) return nlse_fail(NLSE_EINVAL, "too many work items");
   *total_pts = tot;
   *nitems = items;
@@ -92,8 +109,10 @@ struct nlse_batch {
   int nsims, dtype;
   unsigned flags;
   std::vector<nlse_sim_desc> desc;
-  int64_t total_pts, nitems;
+  int64_t total_pts, nitems;  // nitems: of the configured tile
   int nchunks, ngroups;
+  int tx, ty, wg_per_cu;  // tile and persistent workgroups per CU
+  int cus;
   unsigned spin_limit;
   void* psi;
   const void* vpool;
@@ -114,7 +133,7 @@ extern "C" int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc* sims, 
   return NLSE_OK;
 }
 
-static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
+static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st, int stages = 4) {
   // reset the group arrival counters; the error flag before them stays sticky
   hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier + 8, 8 * (int64_t)b->ngroups, st);
   if (e != hipSuccess) return e;
@@ -123,6 +142,9 @@ static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
   L.comp = (b->flags & NLSE_COMPENSATED) ? 1 : 0;
   L.nsteps = (int)nsteps;
   L.nchunks = b->nchunks;
+  L.tx = b->tx;
+  L.ty = b->ty;
+  L.stages = stages;
   L.items = reinterpret_cast<const nlse::BatchItem*>(b->work + b->lay.items);
   L.chunk_off = reinterpret_cast<const int*>(b->work + b->lay.chunks);
   L.psi = b->psi;
@@ -146,8 +168,8 @@ static void destroy_graphs(nlse_batch* b) {
 // every problem as device descriptors, and for W chunks the item offsets
 // (W + 1) followed by four ints per chunk (group a, size a, group b,
 // size b; -1 / 0 for none).  Returns the number of groups.
-static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, std::vector<nlse::BatchItem>& it,
-                         std::vector<int>& chunk) {
+static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, int TX, int TY,
+                         std::vector<nlse::BatchItem>& it, std::vector<int>& chunk) {
   // device descriptors: the same double constants the single-grid path uses
   std::vector<std::vector<nlse::BatchItem>> tiles(nsims);  // row-major tiles of each problem
   std::vector<double> pcost(nsims);                        // estimated cost of one stage
@@ -174,7 +196,7 @@ static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, std::vecto
     s.dt3 = d.dt / 3.0;
     s.dt6 = d.dt / 6.0;
     s.sim = j;
-    const int ntx = (s.nx + nlse::kBatchTX - 1) / nlse::kBatchTX, nty = (s.ny + nlse::kBatchTY - 1) / nlse::kBatchTY;
+    const int ntx = (s.nx + TX - 1) / TX, nty = (s.ny + TY - 1) / TY;
     const double c = (d.order == 4 ? 1.35 : 1.0) * (d.v_offset >= 0 ? 1.1 : 1.0);
     for (int ty = 0; ty < nty; ++ty)
       for (int tx = 0; tx < ntx; ++tx) {
@@ -244,19 +266,21 @@ static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, std::vecto
   return ngroups;
 }
 
-// Test hook (host only, no device work): the schedule nlse_batch_create
-// builds for W chunks.  chunk_out receives 5 W + 1 ints (see plan_schedule),
-// item_out 3 ints per work item (problem, tx, ty), *ngroups the number of
-// groups.  NLSE_ENOMEM if an output is shorter than that.
-extern "C" int nlse_internal_batch_plan(int nsims, const nlse_sim_desc* sims, int W, int* chunk_out,
+// Test hook (host only, no device work): the schedule a batch with tile
+// tx x ty builds for W chunks.  chunk_out receives 5 W + 1 ints (see
+// plan_schedule), item_out 3 ints per work item (problem, tile x index,
+// tile y index), *ngroups the number of groups.  NLSE_ENOMEM if an output is
+// shorter than that.
+extern "C" int nlse_internal_batch_plan(int nsims, const nlse_sim_desc* sims, int W, int tx, int ty, int* chunk_out,
                                         int64_t chunk_len, int* item_out, int64_t item_len, int* ngroups) {
   int64_t tot, items, mb;
   int rc = validate(nsims, sims, NLSE_F32, 0, &tot, &items, &mb);
   if (rc) return rc;
   if (W < 1 || W > kMaxChunks || !chunk_out || !item_out || !ngroups) return nlse_fail(NLSE_EINVAL, "bad argument");
+  if (!tile_compiled(tx, ty)) return nlse_fail(NLSE_EUNSUPPORTED, "tile %dx%d is not compiled", tx, ty);
   std::vector<nlse::BatchItem> it;
   std::vector<int> chunk;
-  const int ng = plan_schedule(nsims, sims, W, it, chunk);
+  const int ng = plan_schedule(nsims, sims, W, tx, ty, it, chunk);
   if ((int64_t)chunk.size() > chunk_len || 3 * (int64_t)it.size() > item_len)
     return nlse_fail(NLSE_ENOMEM, "output arrays too short");
   std::copy(chunk.begin(), chunk.end(), chunk_out);
@@ -278,6 +302,43 @@ extern "C" int nlse_internal_batch_limits(int64_t out[3]) {
   out[0] = kMaxBatchSteps;
   out[1] = kMaxChunks;
   out[2] = 8 * (int64_t)sizeof(unsigned long long);
+  return NLSE_OK;
+}
+
+// Tile, workgroups per CU and the static schedule of a batch: the
+// persistent grid is min(wg_per_cu, what fits) x CUs workgroups; the work
+// items and chunk table are rebuilt and uploaded, and captured graphs (which
+// hold the grid size and tile) are dropped.  Synchronises the stream.
+static int configure(nlse_batch* b, int tx, int ty, int wg_per_cu) {
+  if (!tile_compiled(tx, ty)) return nlse_fail(NLSE_EUNSUPPORTED, "tile %dx%d is not compiled", tx, ty);
+  if (wg_per_cu < 1 || wg_per_cu > 16) return nlse_fail(NLSE_EINVAL, "wg_per_cu must be 1..16");
+  int occ = 0;
+  hipError_t e = nlse_batch_occupancy(b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, tx, ty, &occ);
+  if (e != hipSuccess) return nlse_hip_fail(e, "querying occupancy");
+  if (occ < 1) return nlse_fail(NLSE_EDEVICE, "the batched kernel does not fit on a CU");
+  int64_t items = 0;
+  for (const auto& d : b->desc) items += tiles_of(d, tx, ty);
+  const int64_t nchunks = std::min<int64_t>({(int64_t)std::min(occ, wg_per_cu) * b->cus, items, (int64_t)kMaxChunks});
+  std::vector<nlse::BatchItem> it;
+  std::vector<int> chunk;
+  const int ngroups = plan_schedule(b->nsims, b->desc.data(), (int)nchunks, tx, ty, it, chunk);
+  if ((int64_t)it.size() != items) return nlse_fail(NLSE_EDEVICE, "internal error: schedule lost work items");
+  e = hipStreamSynchronize(b->stream);  // no launch still reads the old tables
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->work + b->lay.items, it.data(), sizeof(nlse::BatchItem) * it.size(),
+                       hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->work + b->lay.chunks, chunk.data(), sizeof(int) * chunk.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return nlse_hip_fail(e, "uploading the batch schedule");
+  destroy_graphs(b);
+  b->tx = tx;
+  b->ty = ty;
+  b->wg_per_cu = wg_per_cu;
+  b->nchunks = (int)nchunks;
+  b->ngroups = ngroups;
+  b->nitems = items;
   return NLSE_OK;
 }
 
@@ -303,17 +364,11 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
       return nlse_fail(NLSE_EINVAL, "problem %d: potential lies outside v_pool", j);
   }
 
-  // persistent grid: as many workgroups as the device holds at once
-  int dev = 0, cus = 0, occ = 0;
+  int dev = 0, cus = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e == hipSuccess) e = nlse_batch_occupancy(dtype, (flags & NLSE_COMPENSATED) ? 1 : 0, &occ);
-  if (e != hipSuccess) return nlse_hip_fail(e, "querying occupancy");
-  if (occ < 1 || cus < 1) return nlse_fail(NLSE_EDEVICE, "the batched kernel does not fit on a CU");
-  // The item pipeline keeps the memory system busy with three workgroups
-  // per CU; more only add barrier arrivals (measured best: 3).
-  occ = std::min(occ, kMaxWgPerCu);
-  int64_t nchunks = std::min<int64_t>({(int64_t)occ * cus, items, (int64_t)kMaxChunks});
+  if (e != hipSuccess) return nlse_hip_fail(e, "querying the device");
+  if (cus < 1) return nlse_fail(NLSE_EDEVICE, "no compute units");
 
   nlse_batch* B = new (std::nothrow) nlse_batch();
   if (!B) return nlse_fail(NLSE_ENOMEM, "host allocation failed");
@@ -323,7 +378,7 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   B->desc.assign(sims, sims + nsims);
   B->total_pts = tot;
   B->nitems = items;
-  B->nchunks = (int)nchunks;
+  B->cus = cus;
   B->spin_limit = kSpinLimit;
   if (const char* sl = getenv("NLSE_BATCH_SPIN_LIMIT")) {
     const long v = strtol(sl, nullptr, 10);
@@ -336,29 +391,110 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   B->stream = static_cast<hipStream_t>(hip_stream);
   B->cap = nullptr;
 
-  std::vector<nlse::BatchItem> it;
-  std::vector<int> chunk;
-  const int ngroups = plan_schedule(nsims, sims, B->nchunks, it, chunk);
-  B->ngroups = ngroups;
-  if ((int64_t)it.size() != items) {
-    delete B;
-    return nlse_fail(NLSE_EDEVICE, "internal error: schedule lost work items");
-  }
   hipStream_t st = B->stream;
-  e = hipMemcpyAsync(B->work + L.items, it.data(), sizeof(nlse::BatchItem) * it.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(B->work + L.chunks, chunk.data(), sizeof(int) * chunk.size(), hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.zero, 256, st);
+  e = nlse_launch_fill_zero(B->work + L.zero, 256, st);
   if (e == hipSuccess) e = nlse_launch_fill_zero(B->work + L.barrier, (int64_t)(L.zero - L.barrier), st);
   if (e == hipSuccess && (flags & NLSE_COMPENSATED)) e = nlse_launch_fill_zero(B->work + L.lo, tot * 8, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e == hipSuccess && !(flags & NLSE_NO_GRAPH)) e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete B;
     return nlse_hip_fail(e, "creating the batch");
   }
+  rc = configure(B, 32, 8, kDefaultWgPerCu);
+  if (rc) {
+    if (B->cap) (void)hipStreamDestroy(B->cap);
+    delete B;
+    return rc;
+  }
   *out = B;
   return NLSE_OK;
+}
+
+extern "C" int nlse_batch_set_config(nlse_batch* b, int tx, int ty, int wg_per_cu) {
+  if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
+  return configure(b, tx, ty, wg_per_cu);
+}
+
+extern "C" int nlse_batch_get_config(const nlse_batch* b, int cfg[3]) {
+  if (!b || !cfg) return nlse_fail(NLSE_EINVAL, "NULL argument");
+  cfg[0] = b->tx;
+  cfg[1] = b->ty;
+  cfg[2] = b->wg_per_cu;
+  return NLSE_OK;
+}
+
+// Cache key of a batch: element type, mode and a hash (FNV-1a) of every
+// problem's shape, scheme, boundary condition and whether it has a potential.
+static std::string batch_key(const nlse_batch* b) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (const auto& d : b->desc) {
+    mix(d.dims[0]);
+    mix(d.dims[1]);
+    mix(d.order);
+    mix(d.bc);
+    mix(d.v_offset >= 0 ? 1 : 0);
+  }
+  char buf[128];
+  snprintf(buf, sizeof buf, "batch t%d c%d n%d h%016llx", b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, b->nsims,
+           (unsigned long long)h);
+  return buf;
+}
+
+// Times stages 1-3 only (they never write Psi or the compensation term), so
+// the fields are left untouched; the accumulator and stage buffers are
+// scratch.  Every candidate runs the whole batch with its own schedule.
+extern "C" int nlse_batch_autotune(nlse_batch* b) {
+  if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
+  const std::string key = batch_key(b);
+  int cached[3];
+  if (nlse_cache_lookup(key, cached) && tile_compiled(cached[0], cached[1]) && cached[2] >= 1 && cached[2] <= 16)
+    return configure(b, cached[0], cached[1], cached[2]);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return nlse_hip_fail(e, "hipEventCreate");
+  }
+  const int reps = (int)std::max<int64_t>(2, std::min<int64_t>(50, (int64_t)3e8 / std::max<int64_t>(b->total_pts, 1)));
+  float best = 1e30f;
+  int best_c[3] = {32, 8, kDefaultWgPerCu};
+  int rc = NLSE_OK;
+  for (const auto& t : nlse::kBatchTiles) {
+    int occ = 0;
+    e = nlse_batch_occupancy(b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, t[0], t[1], &occ);
+    if (e != hipSuccess) break;
+    for (int w = kMinWgPerCu; w <= std::min(kMaxWgPerCu, occ); ++w) {
+      if ((rc = configure(b, t[0], t[1], w)) != NLSE_OK) break;
+      if ((e = enqueue(b, 1, b->stream, 3)) != hipSuccess) break;  // warm-up
+      (void)hipEventRecord(e0, b->stream);
+      if ((e = enqueue(b, reps, b->stream, 3)) != hipSuccess) break;
+      (void)hipEventRecord(e1, b->stream);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (ms < best) {
+        best = ms;
+        best_c[0] = t[0];
+        best_c[1] = t[1];
+        best_c[2] = w;
+      }
+    }
+    if (rc != NLSE_OK || e != hipSuccess) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != NLSE_OK) return rc;
+  if (e != hipSuccess) return nlse_hip_fail(e, "batch autotune launch");
+  rc = configure(b, best_c[0], best_c[1], best_c[2]);
+  if (rc == NLSE_OK) nlse_cache_store(key, best_c, best * 4.0f / 3.0f / reps);
+  return rc;
 }
 
 extern "C" int nlse_batch_step_rk4(nlse_batch* b, int64_t nsteps) {

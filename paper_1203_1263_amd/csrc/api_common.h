@@ -3,7 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <string>
+
 // Store a formatted thread-local message (nlse_last_error) and return code.
 int nlse_fail(int code, const char* fmt, ...);
 // NLSE_EDEVICE with the HIP error text.
 int nlse_hip_fail(hipError_t e, const char* what);
+// Autotuner cache ($NLSE_TUNE_CACHE, one "key|a b c ms" line per entry;
+// the last entry of a key wins).  Lookup returns false without the variable.
+bool nlse_cache_lookup(const std::string& key, int t[3]);
+void nlse_cache_store(const std::string& key, const int t[3], float ms);

@@ -152,18 +152,17 @@ __device__ __forceinline__ ItemArgs<T> decode(const BatchArgs<T>& B, unsigned w)
 }
 #undef NLSE_WORD
 
-template <typename T>
+template <typename T, int TX, int TY>
 struct BatchLds {
-  static constexpr int BSZ = (kBatchTX + 4) * (kBatchTY + 4);
+  static constexpr int BSZ = (TX + 4) * (TY + 4);
   cpx<T> u[2][BSZ];  // stage-input box, alternating between items
   T v[2][BSZ];       // potential box, alternating between items
-  cpx<T> d[(kBatchTX + 2) * (kBatchTY + 2)];
+  cpx<T> d[(TX + 2) * (TY + 2)];
 };
 
 // One stage over the items [i0, i1) of this workgroup's chunk.
-template <typename T, int STAGE, int COMP>
-__device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i1, BatchLds<T>& S) {
-  constexpr int TX = kBatchTX, TY = kBatchTY;
+template <typename T, int STAGE, int COMP, int TX, int TY>
+__device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i1, BatchLds<T, TX, TY>& S) {
   using Regs = TileRegs<T, TX, TY>;
   auto words = [&](int it) { return item_words(B.items, min(it, i1 - 1)); };
   auto issue = [&](const ItemArgs<T>& I, Regs& r) {
@@ -223,9 +222,9 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
   if (it < i1) body(it, ra, rb, wa, wb, 0);
 }
 
-template <typename T, int COMP>
-__global__ __launch_bounds__(kBatchTX* kBatchTY) void batch2d_kernel(BatchArgs<T> B, int nsteps) {
-  __shared__ BatchLds<T> S;
+template <typename T, int COMP, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void batch2d_kernel(BatchArgs<T> B, int nsteps, int stages) {
+  __shared__ BatchLds<T, TX, TY> S;
   const int c = xcd_swizzle(blockIdx.x, gridDim.x);
   const int i0 = B.chunk_off[c], i1 = B.chunk_off[c + 1];
   const int* meta = B.chunk_off + gridDim.x + 1 + 4 * c;
@@ -241,25 +240,32 @@ __global__ __launch_bounds__(kBatchTX* kBatchTY) void batch2d_kernel(BatchArgs<T
     }
     return group_barrier(B.flag, B.arrivals, ga, sa, gb, sb, ++k, B.spin_limit);
   };
+  // stages == 3 (timing only) stops before the stage that writes Psi
   for (int n = 0; n < nsteps; ++n) {
-    batch_stage<T, 1, COMP>(B, i0, i1, S);
+    batch_stage<T, 1, COMP, TX, TY>(B, i0, i1, S);
     if (!sync()) return;
-    batch_stage<T, 2, COMP>(B, i0, i1, S);
+    batch_stage<T, 2, COMP, TX, TY>(B, i0, i1, S);
     if (!sync()) return;
-    batch_stage<T, 3, COMP>(B, i0, i1, S);
+    batch_stage<T, 3, COMP, TX, TY>(B, i0, i1, S);
     if (!sync()) return;
-    batch_stage<T, 4, COMP>(B, i0, i1, S);
-    if (!sync()) return;
+    if (stages == 4) {
+      batch_stage<T, 4, COMP, TX, TY>(B, i0, i1, S);
+      if (!sync()) return;
+    }
   }
 }
 
 template <typename T, int COMP>
-static const void* kernel_ptr() {
-  return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP>);
+static const void* kernel_ptr(int tx, int ty) {
+  if (tx == 32 && ty == 8) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 32, 8>);
+  if (tx == 64 && ty == 4) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 4>);
+  if (tx == 64 && ty == 8) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 8>);
+  return nullptr;
 }
 
 template <typename T, int COMP>
 static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
+  if (L.stages != 3 && L.stages != 4) return hipErrorInvalidValue;
   BatchArgs<T> B;
   B.items = L.items;
   B.chunk_off = L.chunk_off;
@@ -273,8 +279,17 @@ static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
   B.flag = L.barrier + 1;
   B.arrivals = reinterpret_cast<unsigned long long*>(L.barrier + 2);
   B.spin_limit = L.spin_limit;
-  hipLaunchKernelGGL((batch2d_kernel<T, COMP>), dim3(L.nchunks), dim3(kBatchTX * kBatchTY), 0, st, B, L.nsteps);
-  return hipGetLastError();
+#define NLSE_LB(TX_, TY_)                                                                                   \
+  if (L.tx == TX_ && L.ty == TY_) {                                                                         \
+    hipLaunchKernelGGL((batch2d_kernel<T, COMP, TX_, TY_>), dim3(L.nchunks), dim3(TX_ * TY_), 0, st, B, L.nsteps, \
+                       L.stages);                                                                           \
+    return hipGetLastError();                                                                               \
+  }
+  NLSE_LB(32, 8)
+  NLSE_LB(64, 4)
+  NLSE_LB(64, 8)
+#undef NLSE_LB
+  return hipErrorInvalidValue;
 }
 
 }  // namespace nlse
@@ -284,9 +299,10 @@ hipError_t nlse_launch_batch(const nlse::BatchLaunch& L, hipStream_t st) {
   return nlse::launch_typed<double, 0>(L, st);
 }
 
-// Workgroups of the batched kernel that one CU holds at once.
-hipError_t nlse_batch_occupancy(int dtype, int comp, int* blocks_per_cu) {
-  const void* k = dtype == 0 ? (comp ? nlse::kernel_ptr<float, 1>() : nlse::kernel_ptr<float, 0>())
-                             : nlse::kernel_ptr<double, 0>();
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, nlse::kBatchTX * nlse::kBatchTY, 0);
+// Workgroups of the batched kernel with tile tx x ty that one CU holds at once.
+hipError_t nlse_batch_occupancy(int dtype, int comp, int tx, int ty, int* blocks_per_cu) {
+  const void* k = dtype == 0 ? (comp ? nlse::kernel_ptr<float, 1>(tx, ty) : nlse::kernel_ptr<float, 0>(tx, ty))
+                             : nlse::kernel_ptr<double, 0>(tx, ty);
+  if (!k) return hipErrorInvalidValue;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, tx * ty, 0);
 }

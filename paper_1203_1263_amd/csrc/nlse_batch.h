@@ -7,7 +7,9 @@
 
 namespace nlse {
 
-constexpr int kBatchTX = 32, kBatchTY = 8;  // tile of the batched kernel
+// Tiles the batched kernel is compiled for (x-width, y-height); 32 x 8 is
+// the default, the autotuner picks among all three.
+constexpr int kBatchTiles[3][2] = {{32, 8}, {64, 4}, {64, 8}};
 
 // One work item (a tile of one problem) as the device sees it: 128 bytes,
 // read by the kernel as 32 dwords, one per lane.  The physical constants are
@@ -27,6 +29,8 @@ static_assert(sizeof(BatchItem) == 128, "BatchItem is read as 32 dwords");
 
 struct BatchLaunch {
   int dtype, comp, nsteps, nchunks;
+  int tx, ty;  // tile (one of kBatchTiles)
+  int stages;  // RK4 stages run per step: 4, or 3 for timing (Psi is not written)
   const BatchItem* items;
   const int* chunk_off;  // nchunks + 1 item offsets, then per chunk its group
                          // (-1: the chunk owns whole problems), then the group size
@@ -41,4 +45,4 @@ struct BatchLaunch {
 }  // namespace nlse
 
 hipError_t nlse_launch_batch(const nlse::BatchLaunch& L, hipStream_t st);
-hipError_t nlse_batch_occupancy(int dtype, int comp, int* blocks_per_cu);
+hipError_t nlse_batch_occupancy(int dtype, int comp, int tx, int ty, int* blocks_per_cu);

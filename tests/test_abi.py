@@ -144,26 +144,30 @@ def test_batch_create_checks_pools_before_launch():
     assert e.value.code == nlse.NLSE_ENOMEM
 
 
-def _plan(descs, W):
+def _plan(descs, W, tile=(32, 8)):
     lib = nlse.load_library()
     f = lib.nlse_internal_batch_plan
     f.restype = ctypes.c_int
     n = len(descs)
     arr = (nlse.SimDesc * n)(*descs)
-    nitems = sum(((d.dims[0] + 31) // 32) * ((d.dims[1] + 7) // 8) for d in descs)
+    tx, ty = tile
+    nitems = sum(((d.dims[0] + tx - 1) // tx) * ((d.dims[1] + ty - 1) // ty) for d in descs)
     chunk = (ctypes.c_int * (5 * W + 1))()
     items = (ctypes.c_int * (3 * nitems))()
     ng = ctypes.c_int()
-    rc = f(n, arr, W, chunk, ctypes.c_int64(5 * W + 1), items, ctypes.c_int64(3 * nitems), ctypes.byref(ng))
+    rc = f(n, arr, W, tx, ty, chunk, ctypes.c_int64(5 * W + 1), items, ctypes.c_int64(3 * nitems),
+           ctypes.byref(ng))
     assert rc == 0, lib.nlse_last_error()
     c = list(chunk)
     return c[:W + 1], [tuple(c[W + 1 + 4 * k:W + 5 + 4 * k]) for k in range(W)], list(items), ng.value, nitems
 
 
+@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (64, 8)], ids=["32x8", "64x4", "64x8"])
 @pytest.mark.parametrize("seed,nsims,W", [(0, 40, 64), (1, 512, 768), (2, 7, 200), (3, 3, 1), (4, 30, 4096)])
-def test_batch_schedule_invariants(seed, nsims, W):
-    """The batched integrator's static schedule (host logic): every tile of
-    every problem in exactly one chunk; a problem's tiles in consecutive
+def test_batch_schedule_invariants(seed, nsims, W, tile):
+    """The batched integrator's static schedule (host logic), for every tile
+    the batched kernel is compiled for: every tile of every problem in
+    exactly one chunk; a problem's tiles in consecutive
     chunks; a problem spread over several chunks is one group whose size is
     its chunk span and which every chunk of the span (and no other) names;
     chunk costs balanced to within one tile of the fair share."""
@@ -175,12 +179,13 @@ def test_batch_schedule_invariants(seed, nsims, W):
         descs.append(_desc(dims=(nx, ny, 1), order=int(g.choice([2, 4])), psi_offset=off,
                            v_offset=-1 if j % 2 else 0))
         off += nx * ny
-    offs, meta, items, ngroups, nitems = _plan(descs, W)
+    offs, meta, items, ngroups, nitems = _plan(descs, W, tile)
+    tx, ty = tile
     assert offs[0] == 0 and offs[-1] == nitems and all(a <= b for a, b in zip(offs, offs[1:]))
     trip = [tuple(items[3 * i:3 * i + 3]) for i in range(nitems)]
     assert len(set(trip)) == nitems  # no tile twice
     sim = np.array(items[0::3])
-    want = [((d.dims[0] + 31) // 32) * ((d.dims[1] + 7) // 8) for d in descs]
+    want = [((d.dims[0] + tx - 1) // tx) * ((d.dims[1] + ty - 1) // ty) for d in descs]
     assert np.array_equal(np.bincount(sim, minlength=nsims), want)
     chunk_of = np.searchsorted(np.array(offs), np.arange(nitems), side="right") - 1
     span = {}

@@ -78,6 +78,72 @@ def test_batch_matches_oracle_and_single_grid(dtype, comp, graph):
     b.close()
 
 
+@pytest.mark.parametrize("tile,wg", [((64, 4), 2), ((64, 8), 4), ((32, 8), 5), ((64, 4), 16)],
+                         ids=["64x4-w2", "64x8-w4", "32x8-w5", "64x4-w16"])
+def test_every_tile_and_grid_size_equals_single_grid(tile, wg):
+    """Every configuration the autotuner may choose: the batch with tile
+    (tx, ty) and wg workgroups per CU is bitwise equal to single grids run
+    with the same tile, and within 1e-5 of the oracle (compensated FP32),
+    after a reconfiguration from the default and with graph replays."""
+    import torch
+    from paper_1203_1263_amd.nlse import Batch, Grid
+    from gpu_util import to_dev, pot_dev
+    probs, dts = small_batch(11)
+    b2 = Batch(probs, dts, compensated=True)  # created with the default configuration
+    b2.set_config(tile[0], tile[1], wg)
+    assert b2.config() == (tile[0], tile[1], wg)
+    n = 9
+    b2.step(4)
+    b2.step(5)
+    b2.status()
+    torch.cuda.synchronize()
+    for j, (p, dt) in enumerate(zip(probs, dts)):
+        psi = to_dev(p.psi0, "f32")
+        g = Grid(psi, p.h, p.a, p.s, V=pot_dev(p.V, "f32"), compensated=True)
+        g.set_tile(p.order, (tile[0], tile[1], 1))
+        g.step(dt, n, order=p.order, bc=p.bc)
+        torch.cuda.synchronize()
+        assert torch.equal(psi, b2.field(j)), f"problem {j} differs from its single-grid run"
+        g.close()
+        ref = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, n, V=p.V, order=p.order, bc=p.bc)
+        assert rel_l2(b2.field(j).cpu().numpy().astype(np.complex128), ref) < 1e-5, f"problem {j}"
+    b2.close()
+
+
+def test_autotune_keeps_fields_and_caches_its_choice(tmp_path, monkeypatch):
+    """The batch autotuner leaves the fields and the compensation term as
+    they were (a run after tuning equals a run of an untuned batch with the
+    chosen configuration), picks a compiled tile, and a second batch of the
+    same problems reads the choice from $NLSE_TUNE_CACHE."""
+    import torch
+    from paper_1203_1263_amd.nlse import Batch
+    probs, dts = small_batch(13)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("NLSE_TUNE_CACHE", str(cache))
+    b = Batch(probs, dts, compensated=True)
+    b.step(3)
+    before = b.pool.clone()
+    b.autotune()
+    torch.cuda.synchronize()
+    assert torch.equal(before, b.pool)
+    cfg = b.config()
+    assert (cfg[0], cfg[1]) in ((32, 8), (64, 4), (64, 8)) and 2 <= cfg[2] <= 5
+    b.step(4)
+    b.status()
+    ref = Batch(probs, dts, compensated=True)
+    ref.set_config(*cfg)
+    ref.step(7)
+    ref.status()
+    torch.cuda.synchronize()
+    assert torch.equal(ref.pool, b.pool)
+    assert cache.exists() and "batch" in cache.read_text()
+    b3 = Batch(probs, dts, compensated=True)
+    b3.autotune()
+    assert b3.config() == cfg
+    for x in (b, ref, b3):
+        x.close()
+
+
 def test_graph_replays_match_direct_launches():
     """Three replays of the captured graph, with other device work and
     synchronisations between them, each bitwise equal to direct launches."""
