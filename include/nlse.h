@@ -167,6 +167,30 @@ int nlse_run_frames(nlse_grid *g, int order, int bc, double dt, int64_t chunk,
 int nlse_mass_energy(nlse_grid *g, int order, int bc, double *mass,
                      double *energy);
 
+/* Mass and energy of a field without a grid and without any device
+ * allocation: for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Computes exactly what nlse_mass_energy computes for a grid of this shape,
+ * these parameters and this potential (the same bits): psi_dev holds Npts
+ * interleaved complex values of dtype, V_dev a real array of the same shape
+ * or NULL (V == 0); both are only read.  Where nlse_mass_energy stores the
+ * 2SHOC step-1 values D in the grid's workspace, this one recomputes D at
+ * each point where the Laplacian needs it (about 3x slower in 3D).  Scratch:
+ * the per-workgroup partial sums and the three result doubles live in a
+ * library-owned static device array of 1.5 MiB (one per device, kept until
+ * the process ends), which limits fields to 2^28 points (larger:
+ * NLSE_EINVAL, nothing launched).  Every value in it is written before it is
+ * read in the same call, so nothing needs clearing.  Calls that overlap on
+ * one device (several host threads, or streams running concurrently) share
+ * that array and race: serialise them.  No hipMalloc, hipFree or other
+ * allocating call is made.  Runs on hip_stream (NULL = default stream) and
+ * synchronises it; returns NLSE_EUNSTABLE (after writing both values) if
+ * either is not finite. */
+int nlse_mass_energy_noalloc(int ndim, const int64_t dims[3], double h,
+                             double a, double s, int dtype, int order, int bc,
+                             const void *psi_dev, const void *V_dev,
+                             void *hip_stream, double *mass, double *energy);
+
 /* Copy the compensation term (Npts complex FP32 values, same layout as Psi)
  * out to / in from a device buffer.  lo_dev == NULL in nlse_set_state resets
  * it to zero (call this after overwriting Psi).  Grids without

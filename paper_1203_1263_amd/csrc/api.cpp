@@ -570,6 +570,58 @@ extern "C" int nlse_mass_energy(nlse_grid* g, int order, int bc, double* mass, d
   return NLSE_OK;
 }
 
+extern "C" int nlse_mass_energy_noalloc(int ndim, const int64_t dims[3], double h, double a, double s, int dtype,
+                                        int order, int bc, const void* psi_dev, const void* V_dev, void* hip_stream,
+                                        double* mass, double* energy) {
+  Shape sh;
+  int rc = check_shape(ndim, dims, &sh);
+  if (rc) return rc;
+  if (dtype != NLSE_F32 && dtype != NLSE_F64) return fail(NLSE_EINVAL, "dtype must be NLSE_F32 or NLSE_F64");
+  rc = check_scheme(order, bc);
+  if (rc) return rc;
+  if (!(h > 0) || !std::isfinite(h)) return fail(NLSE_EINVAL, "h must be finite and > 0");
+  if (!(a > 0) || !std::isfinite(a)) return fail(NLSE_EINVAL, "a must be finite and > 0");
+  if (!std::isfinite(s)) return fail(NLSE_EINVAL, "s must be finite");
+  if (!psi_dev) return fail(NLSE_EINVAL, "psi_dev is NULL");
+  if (((uintptr_t)psi_dev) % (dtype == NLSE_F32 ? 8 : 16))
+    return fail(NLSE_EINVAL, "psi_dev is not aligned to one complex element");
+  if (V_dev && ((uintptr_t)V_dev) % (dtype == NLSE_F32 ? 4 : 8))
+    return fail(NLSE_EINVAL, "V_dev is not aligned to one real element");
+  if (!mass || !energy) return fail(NLSE_EINVAL, "mass/energy pointers are NULL");
+  const int64_t max_pts = nlse::kStaticReduceBlocks * nlse::kReduceChunk;
+  if (sh.npts > max_pts)
+    return fail(NLSE_EINVAL, "grid of %lld points exceeds the %lld points the static scratch serves",
+                (long long)sh.npts, (long long)max_pts);
+  nlse::ReduceLaunch R;
+  R.ndim = ndim;
+  R.dtype = dtype;
+  R.order = order;
+  R.bc = bc;
+  for (int d = 0; d < 3; ++d) R.n[d] = sh.n[d];
+  R.psi = psi_dev;
+  R.V = V_dev;
+  R.a = a;
+  R.s = s;
+  R.h = h;
+  R.dscratch = nullptr;  // 2SHOC: D recomputed where it is needed, nothing stored
+  hipError_t e = nlse_static_reduce_scratch(&R.partials, &R.out);
+  if (e != hipSuccess) return hip_fail(e, "looking up the static reduction scratch");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  e = nlse_launch_reduce(R, st);
+  if (e != hipSuccess) return hip_fail(e, "reduction launch");
+  double host[3];
+  e = hipMemcpyAsync(host, R.out, sizeof host, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "copying the reduction result");
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "stream synchronize");
+  const double hd = std::pow(h, (double)ndim);
+  *mass = hd * host[0];
+  *energy = hd * (host[1] + host[2]);
+  if (!std::isfinite(*mass) || !std::isfinite(*energy))
+    return fail(NLSE_EUNSTABLE, "mass %g / energy %g is not finite", *mass, *energy);
+  return NLSE_OK;
+}
+
 extern "C" int nlse_get_state(nlse_grid* g, void* lo_dev) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
   if (!(g->flags & NLSE_COMPENSATED)) return fail(NLSE_EINVAL, "grid has no compensation term");

@@ -44,6 +44,11 @@ constexpr int kReduceChunk = 4096;  // points per reduction workgroup (fixed)
 
 inline int64_t reduce_blocks(int64_t npts) { return (npts + kReduceChunk - 1) / kReduceChunk; }
 
+// Reduction workgroups the library's static scratch holds partial sums for
+// (nlse_mass_energy_noalloc): grids of at most kStaticReduceBlocks *
+// kReduceChunk = 2^28 points.
+constexpr int64_t kStaticReduceBlocks = (int64_t)1 << 16;
+
 }  // namespace nlse
 
 hipError_t nlse_launch_stage(const nlse::StageLaunch& L, hipStream_t st);
@@ -56,6 +61,10 @@ hipError_t nlse_launch_fused3d(const nlse::StageLaunch& L, const void* psi_in, v
 hipError_t nlse_launch_fused3d_pair0(const nlse::StageLaunch& L, const void* psi, void* acc, void* mid, double dt,
                                      hipStream_t st);
 hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st);
+// Device addresses, on the current device, of the library's static reduction
+// scratch: kStaticReduceBlocks * 3 partial doubles and 3 result doubles
+// (looked up once per device with hipGetSymbolAddress).
+hipError_t nlse_static_reduce_scratch(double** partials, double** out);
 // Whole-grid 1D integrator (one workgroup, grid on chip): nsteps RK4 steps of
 // size dt in one launch, updating L.psi (and L.lo) in place; bitwise equal
 // to the per-stage kernels.  Grids of 3 .. nlse_resident1d_max_points(dtype).

@@ -12,6 +12,7 @@
 // a fixed order.  The result is bitwise reproducible and independent of the
 // stage kernels' tile shapes.
 #include <algorithm>
+#include <mutex>
 
 #include "nlse_device.hpp"
 #include "nlse_internal.h"
@@ -126,11 +127,21 @@ __global__ __launch_bounds__(256) void reduce_d_kernel(View<T, ND> g, int bc, in
   }
 }
 
-// Scheme Laplacian at an interior point (2SHOC from the stored D).
-template <typename T, int ND>
-__device__ cpx<double> L_at(const View<T, ND>& g, int order, const cpx<double>* D, const int c[3]) {
+// 2SHOC D of a point: read from the stored pass, or (no D array) computed
+// on the spot by the same function the stored pass runs, so both give the
+// same value.
+template <bool STORED, typename T, int ND>
+__device__ __forceinline__ cpx<double> D_get(const View<T, ND>& g, int bc, const cpx<double>* D, const int c[3]) {
+  if constexpr (STORED) return D[lin(g, c)];
+  else return D_at(g, bc, c);
+}
+
+// Scheme Laplacian at an interior point (2SHOC from the stored D, or from D
+// recomputed at the point and its 2d face neighbours).
+template <bool STORED, typename T, int ND>
+__device__ cpx<double> L_at(const View<T, ND>& g, int order, int bc, const cpx<double>* D, const int c[3]) {
   if (order == 2) return cd2_at(g, c);
-  cpx<double> D0 = D[lin(g, c)];
+  cpx<double> D0 = D_get<STORED>(g, bc, D, c);
   cpx<double> u0 = ldd(g, c);
   double fr = 0.0, fi = 0.0, er = 0.0, ei = 0.0;
 #pragma unroll
@@ -138,7 +149,7 @@ __device__ cpx<double> L_at(const View<T, ND>& g, int order, const cpx<double>* 
     for (int sgn = -1; sgn <= 1; sgn += 2) {
       int p[3] = {c[0], c[1], c[2]};
       p[d] += sgn;
-      cpx<double> Df = D[lin(g, p)];
+      cpx<double> Df = D_get<STORED>(g, bc, D, p);
       fr += Df.re - D0.re;
       fi += Df.im - D0.im;
     }
@@ -164,8 +175,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename T, int ND>
-__global__ __launch_bounds__(256) void reduce_partial_kernel(View<T, ND> g, int order, const cpx<double>* D,
+template <bool STORED, typename T, int ND>
+__global__ __launch_bounds__(256) void reduce_partial_kernel(View<T, ND> g, int order, int bc, const cpx<double>* D,
                                                              int64_t npts, double* partials) {
   __shared__ double red[3][4];
   const int64_t b0 = (int64_t)blockIdx.x * kReduceChunk;
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(256) void reduce_partial_kernel(View<T, ND> g, int 
     m += rho;
     pot += vd(g, c) * rho - 0.5 * g.s * rho * rho;
     if (!on_bnd(g, c)) {
-      cpx<double> L = L_at(g, order, D, c);
+      cpx<double> L = L_at<STORED>(g, order, bc, D, c);
       kin += -g.a * (u.re * L.re + u.im * L.im);
     }
   }
@@ -243,16 +254,19 @@ static hipError_t reduce_dim(const ReduceLaunch& R, hipStream_t st) {
   const int64_t npts = R.n[0] * R.n[1] * R.n[2];
   const int64_t nb = reduce_blocks(npts);
   cpx<double>* D = nullptr;
-  if (R.order == 4) {
-    if (!R.dscratch) return hipErrorInvalidValue;
+  if (R.order == 4 && R.dscratch) {
     D = static_cast<cpx<double>*>(R.dscratch);
     const int64_t blocks = std::min<int64_t>((npts + 255) / 256, 8192);
     hipLaunchKernelGGL((reduce_d_kernel<T, ND>), dim3((unsigned)blocks), dim3(256), 0, st, g, R.bc, npts, D);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((reduce_partial_kernel<T, ND>), dim3((unsigned)nb), dim3(256), 0, st, g, R.order, D, npts,
-                     R.partials);
+  if (D)
+    hipLaunchKernelGGL((reduce_partial_kernel<true, T, ND>), dim3((unsigned)nb), dim3(256), 0, st, g, R.order, R.bc,
+                       D, npts, R.partials);
+  else
+    hipLaunchKernelGGL((reduce_partial_kernel<false, T, ND>), dim3((unsigned)nb), dim3(256), 0, st, g, R.order,
+                       R.bc, D, npts, R.partials);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(256), 0, st, R.partials, nb, R.out);
@@ -298,4 +312,36 @@ hipError_t nlse_launch_fill_zero(void* p, int64_t nbytes, hipStream_t st) {
   hipLaunchKernelGGL(nlse::fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
                      static_cast<uint32_t*>(p), nw);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- static scratch
+
+// Partial sums (three per reduction workgroup) and the three result doubles
+// of nlse_mass_energy_noalloc, so that entry point needs no device
+// allocation.  A file-scope device array: every device the library runs on
+// holds its own copy from module load until the process ends.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[nlse::kStaticReduceBlocks * 3 + 32];
+
+hipError_t nlse_static_reduce_scratch(double** partials, double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *partials = addr[dev];
+  *out = addr[dev] + nlse::kStaticReduceBlocks * 3;
+  return hipSuccess;
 }

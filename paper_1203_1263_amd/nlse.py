@@ -74,6 +74,9 @@ def load_library() -> ctypes.CDLL:
         "nlse_set_potential": (ctypes.c_int, [vp, vp]),
         "nlse_step_rk4": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64]),
         "nlse_mass_energy": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, dp, dp]),
+        "nlse_mass_energy_noalloc": (ctypes.c_int, [ctypes.c_int, i64p, ctypes.c_double, ctypes.c_double,
+                                                    ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                                    vp, vp, vp, dp, dp]),
         "nlse_run_frames": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int64,
                                            ctypes.c_int64, vp, vp, ctypes.c_size_t]),
         "nlse_get_state": (ctypes.c_int, [vp, vp]),
@@ -172,6 +175,16 @@ def nlse_mass_energy(g, order: int, bc: int) -> Tuple[float, float]:
     m, e = ctypes.c_double(), ctypes.c_double()
     _check(load_library().nlse_mass_energy(g, order, bc, ctypes.byref(m), ctypes.byref(e)),
            "nlse_mass_energy")
+    return m.value, e.value
+
+
+def nlse_mass_energy_noalloc(ndim: int, dims, h: float, a: float, s: float, dtype: int, order: int, bc: int,
+                             psi_ptr: int, v_ptr: Optional[int], stream_ptr: Optional[int]) -> Tuple[float, float]:
+    d = (ctypes.c_int64 * 3)(*dims)
+    m, e = ctypes.c_double(), ctypes.c_double()
+    _check(load_library().nlse_mass_energy_noalloc(ndim, d, h, a, s, dtype, order, bc, psi_ptr, v_ptr, stream_ptr,
+                                                   ctypes.byref(m), ctypes.byref(e)),
+           "nlse_mass_energy_noalloc")
     return m.value, e.value
 
 

@@ -248,3 +248,20 @@ def test_batch_barrier_targets_cannot_wrap():
     with pytest.raises(nlse.NLSEError) as e:
         nlse.nlse_batch_step_rk4(None, max_steps + 1)
     assert e.value.code == nlse.NLSE_EINVAL and "nsteps" in str(e.value)
+
+
+def test_noalloc_mass_energy_rejects_before_any_device_call():
+    """nlse_mass_energy_noalloc validates on the host first: a field beyond
+    its static scratch (2^28 points) and bad arguments return NLSE_EINVAL
+    without touching a device (this runs without a GPU)."""
+    ok = dict(ndim=3, dims=[64, 64, 64], h=0.1, a=1.0, s=1.0, dtype=nlse.NLSE_F32, order=2,
+              bc=nlse.NLSE_BC_DIRICHLET, psi_ptr=0x100000, v_ptr=None, stream_ptr=None)
+    for bad in (dict(dims=[1024, 1024, 257]), dict(dims=[2, 64, 64]), dict(h=0.0), dict(a=-1.0),
+                dict(order=3), dict(bc=7), dict(dtype=5), dict(psi_ptr=None), dict(psi_ptr=0x100004)):
+        args = dict(ok, **bad)
+        with pytest.raises(nlse.NLSEError) as e:
+            nlse.nlse_mass_energy_noalloc(**args)
+        assert e.value.code == nlse.NLSE_EINVAL, bad
+    with pytest.raises(nlse.NLSEError) as e:
+        nlse.nlse_mass_energy_noalloc(**dict(ok, dims=[1024, 1024, 257]))
+    assert "static scratch" in str(e.value)
