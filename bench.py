@@ -9,8 +9,11 @@ compensated FP64 final RK4 combination, 2SHOC Laplacian, MSD boundaries.  A
 inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line with the throughput, the roofline position of the stage
-kernel (algorithmic bytes / measured time against 8 TB/s HBM) and a CPU
-baseline (the FP64 oracle timed on a bounded sample on the host cores).
+kernel (algorithmic bytes / measured time against 8 TB/s HBM), a CPU
+baseline (the FP64 oracle timed on a bounded sample on the host cores) and a
+summary of the learned surrogate (trained here on trajectories of the
+integrator: error against RK4 after 1..10 blocks of 16 steps and speedup over
+16 RK4 steps at batch 1 and 64).
 """
 from __future__ import annotations
 
@@ -50,6 +53,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="grid extent per axis (default 256)")
     ap.add_argument("--plain", action="store_true", help="plain FP32 (no compensation)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip the surrogate summary (trajectory generation, training and timing, ~15 s)")
     ap.add_argument("--cpu-steps", type=int, default=0,
                     help="oracle steps of each CPU-baseline run (0: 40 on all cores, 6 on one)")
     ap.add_argument("--tile", type=int, nargs=3, default=None, metavar=("TX", "TY", "CZ"),
@@ -309,10 +314,33 @@ def main():
                      "avg_launch_us": avg_launch_s * 1e6},
         "mass": M, "energy": E,
     }
+    g.close()
+    del psi, V
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_steps, n)
-    g.close()
+    if not args.no_surrogate:
+        out["surrogate"] = surrogate_summary(args)
     print(json.dumps(out), flush=True)
+
+
+def surrogate_summary(args):
+    """The learned-surrogate workload in short: generate its trajectories
+    with the batched integrator, train it with the library's kernels, and
+    report its error against RK4 and its speedup over 16 RK4 steps."""
+    from paper_1203_1263_amd import surrogate_train as st
+    res, m, _ = st.run(args.trajectories, args.iters)
+    m.close()
+    keep = ("trajectories", "pairs", "iters", "seconds_generate", "seconds_train", "rel_l2_after_1_blocks",
+            "rel_l2_after_10_blocks", "rel_l2_after_k_blocks", "blocks_within_1e-2", "rel_l2_one_block_mean",
+            "mass_drift_per_block_max", "fallbacks", "blocks", "rel_l2_guarded")
+    out = {k: res[k] for k in keep}
+    for b in ("speedup_b1", "speedup_b64"):
+        out[b] = {k: res[b][k] for k in ("batch", "ms_rk4_16_steps", "ms_surrogate_block", "speedup")}
+    # the speedup holds for as many blocks as stay within the 1e-2 error bar
+    out["speedup_within_1e-2"] = {"blocks": res["blocks_within_1e-2"],
+                                  "batch_1": res["speedup_b1"]["speedup"], "batch_64": res["speedup_b64"]["speedup"]}
+    out["forward_b64"] = {"TFLOP/s": res["speedup_b64"]["forward_tflops"], "GB/s": res["speedup_b64"]["forward_gbs"]}
+    return out
 
 
 if __name__ == "__main__":

@@ -11,9 +11,14 @@ Initial conditions: 2-8 seeded singly charged vortices on a unit background.
    100 (psi(t), psi(t + 16 dt)) pairs per trajectory.  Trajectories are split
    90/5/5 into train / validation / test.
 2. Training: Adam on the mean squared error of the 16-step increment, with
-   the library's forward / backward / optimiser kernels.
-3. Evaluation on test trajectories: relative L2 distance to RK4 after 1 and
-   10 surrogate blocks, relative mass and energy drift per block, fallback
+   the library's forward / backward / optimiser kernels.  With pushforward
+   p > 0, after the first 30% of the iterations a fraction p of the
+   iterations trains on the network's own prediction of psi(t + 16 dt)
+   (forward pass plus MSD projection, no gradient through it) as input and
+   psi(t + 32 dt) as target, so the network also sees inputs carrying its
+   own one-block error (the pushforward trick of learned simulators).
+3. Evaluation on test trajectories: relative L2 distance to RK4 after each
+   of 1 .. 10 surrogate blocks (and the largest block count within 1e-2), relative mass and energy drift per block, fallback
    count of the guarded advance (mass drift tolerance 1e-3), and the time of
    one block (surrogate + mass check) against 16 RK4 steps at batch 1 and
    batch 64.
@@ -90,7 +95,8 @@ def init_params(seed: int = 0, last_scale: float = 0.1):
     return np.concatenate(out).astype(np.float32)
 
 
-def train(snaps, train_idx, iters: int, batch: int = 32, lr: float = 1e-3, seed: int = 0, log_every: int = 100):
+def train(snaps, train_idx, iters: int, batch: int = 32, lr: float = 1e-3, seed: int = 0, log_every: int = 100,
+          pushforward: float = 0.0):
     import torch
     params = torch.from_numpy(init_params(seed)).cuda()
     m = Surrogate(N, N, max(batch, 64), H_STEP, params=params)
@@ -98,15 +104,23 @@ def train(snaps, train_idx, iters: int, batch: int = 32, lr: float = 1e-3, seed:
     npairs = snaps.shape[1] - 1
     x = torch.empty((batch, N, N), dtype=torch.complex64, device="cuda")
     y = torch.empty_like(x)
+    x0 = torch.empty_like(x)
     hist = []
     t0 = time.perf_counter()
     for it in range(iters):
         tr = g.choice(train_idx, size=batch)
-        k = g.integers(0, npairs, size=batch)
+        push = pushforward > 0 and it >= 0.3 * iters and g.random() < pushforward
+        k = g.integers(0, npairs - (1 if push else 0), size=batch)
         ti = torch.from_numpy(tr).cuda()
         ki = torch.from_numpy(k).cuda()
-        x.copy_(snaps[ti, ki])
-        y.copy_(snaps[ti, ki + 1])
+        if push:
+            x0.copy_(snaps[ti, ki])
+            m.forward(x0, x)
+            m.project_msd(x0, x)
+            y.copy_(snaps[ti, ki + 2])
+        else:
+            x.copy_(snaps[ti, ki])
+            y.copy_(snaps[ti, ki + 1])
         lr_t = lr * 0.5 * (1 + math.cos(math.pi * it / iters)) + 1e-5
         want = (it % log_every == 0) or it == iters - 1
         loss = m.train_step(x, y, lr_t, want_loss=want)
@@ -124,18 +138,28 @@ def _rel(a, b):
 
 
 def evaluate(m, snaps, test_idx):
-    """Relative L2 to RK4 after 1 and 10 blocks; mass drift per block."""
+    """Relative L2 to RK4 after 1 .. 10 blocks (from each test trajectory's
+    first snapshot), the largest block count within 1e-2, and the one-block
+    error and mass drift over the trajectories."""
     import torch
     out = {}
     x0 = snaps[test_idx, 0].contiguous()
-    nb = len(test_idx)
     y = x0
+    curve = []
     for k in range(1, 11):
         pred = m.forward(y)
         m.project_msd(y, pred)
         y = pred
-        if k in (1, 10):
-            out[f"rel_l2_after_{k}_blocks"] = _rel(y, snaps[test_idx, k])
+        curve.append(_rel(y, snaps[test_idx, k]))
+    out["rel_l2_after_1_blocks"] = curve[0]
+    out["rel_l2_after_10_blocks"] = curve[-1]
+    out["rel_l2_after_k_blocks"] = curve
+    n_ok = 0  # leading blocks whose error stays within 1e-2
+    for e in curve:
+        if e > 1e-2:
+            break
+        n_ok += 1
+    out["blocks_within_1e-2"] = n_ok
     # one-block errors from every snapshot of the test trajectories
     errs, drifts = [], []
     for k in range(0, snaps.shape[1] - 1, 10):
@@ -213,7 +237,8 @@ def speedup(m, snaps, batch: int):
             "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9}
 
 
-def run(ntraj: int = 200, iters: int = 3000, batch: int = 32, lr: float = 1e-3, seed: int = 0):
+def run(ntraj: int = 200, iters: int = 3000, batch: int = 32, lr: float = 1e-3, seed: int = 0,
+        pushforward: float = 0.0):
     import torch
     t0 = time.perf_counter()
     snaps = generate(ntraj)
@@ -224,8 +249,10 @@ def run(ntraj: int = 200, iters: int = 3000, batch: int = 32, lr: float = 1e-3, 
     train_idx, val_idx, test_idx = perm[:ntr], perm[ntr:ntr + nva], perm[ntr + nva:]
     if len(test_idx) == 0:
         test_idx = val_idx
-    m, params, hist, t_train = train(snaps, train_idx, iters, batch=batch, lr=lr, seed=seed)
+    m, params, hist, t_train = train(snaps, train_idx, iters, batch=batch, lr=lr, seed=seed,
+                                     pushforward=pushforward)
     res = {"trajectories": ntraj, "pairs": ntraj * (snaps.shape[1] - 1), "iters": iters, "batch": batch,
+           "pushforward": pushforward,
            "seconds_generate": t_gen, "seconds_train": t_train, "loss_first": hist[0][1], "loss_last": hist[-1][1]}
     ti = torch.from_numpy(np.asarray(test_idx)).cuda()
     res.update(evaluate(m, snaps, ti))
@@ -242,8 +269,9 @@ def main():
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--pushforward", type=float, default=0.0)
     a = ap.parse_args()
-    res, _, _ = run(a.trajectories, a.iters, a.batch, a.lr)
+    res, _, _ = run(a.trajectories, a.iters, a.batch, a.lr, pushforward=a.pushforward)
     print(json.dumps(res), flush=True)
 
 
