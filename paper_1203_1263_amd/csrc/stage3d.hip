@@ -189,20 +189,21 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
     }
   };
 
-  // ---- prologue: planes zb-1 .. zb+LOOK-1 straight into LDS
-  {
-    const int last = min(zb + LOOK - 1, zmax);
-    for (int z = zb - 1; z <= last; ++z) {
-      cpx<T> r[PF];
-      load_regs(z, r);
-      put_regs(z, r);
-    }
-  }
+  // ---- prologue: planes zb-1 .. zb+LOOK-1 into LDS.  Every load of the
+  // prologue (those planes, the column below them, the first pipeline set)
+  // is issued before the first LDS store, so the workgroup waits for one
+  // memory round trip instead of one per plane.
+  cpx<T> pro[LOOK + 1][PF];
+#pragma unroll
+  for (int k = 0; k <= LOOK; ++k) load_regs(min(zb - 1 + k, zmax), pro[k]);
   cpx<T> um2 = czero<T>();
   if constexpr (ORDER == 4) um2 = A.uin[(int64_t)max(zb - 2, 0) * ps + qidx];
   Pipe pa, pb, pc;
   load_pipe(min(zb + LOOK, zmax), zb, pa);
   if constexpr (DEPTH == 2) load_pipe(min(zb + 1 + LOOK, zmax), min(zb + 1, ze - 1), pb);
+#pragma unroll
+  for (int k = 0; k <= LOOK; ++k)
+    if (zb - 1 + k <= zmax) put_regs(zb - 1 + k, pro[k]);
   __syncthreads();
 
   cpx<T> dm = czero<T>();  // D of plane z-1 at the q column
