@@ -66,8 +66,13 @@ enum { kEpiRelu = 0, kEpiLast = 1, kEpiDgrad = 2 };
 // next tile is loaded into registers while the current tile is computed.
 // LDS rows are padded by 16 bytes (weights: K + 8, pixels: CIN + 8 BF16
 // values) so the 16-byte operand reads of 16 lanes hit distinct banks.
-template <int CIN, int COUT, int EPI>
-__global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles) {
+// NW waves per workgroup, each owning 16 / NW pixel rows of the tile and
+// every output channel block; launch bounds ask for two workgroups per CU
+// (NW / 2 waves per SIMD).
+template <int CIN, int COUT, int EPI, int NW>
+__global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, int ntiles) {
+  constexpr int NTH = 64 * NW;  // threads
+  constexpr int RPW = 16 / NW;  // pixel rows per wave
   constexpr int K = 9 * CIN;
   constexpr int KP = K + 8;    // padded weight row
   constexpr int CP = CIN + 8;  // padded input pixel
@@ -75,7 +80,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles)
   constexpr int NCB = COUT / 16;
   constexpr int CH = CIN / 8;  // 16-byte chunks per input pixel
   constexpr int NCHUNK = 18 * 18 * CH;
-  constexpr int NLD = (NCHUNK + 255) / 256;
+  constexpr int NLD = (NCHUNK + NTH - 1) / NTH;
   __shared__ __attribute__((aligned(16))) uint16_t sIn[18 * 18 * CP];
   __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * KP];
 
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles)
   {
     const uint4* src = reinterpret_cast<const uint4*>(a.w);
     uint4* dst = reinterpret_cast<uint4*>(sW);
-    for (int i = tid; i < COUT * K / 8; i += 256) {
+    for (int i = tid; i < COUT * K / 8; i += NTH) {
       const int row = i / (K / 8), c = i - row * (K / 8);
       dst[row * (KP / 8) + c] = src[i];
     }
@@ -100,7 +105,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles)
     const int64_t img = (int64_t)b * a.H * a.W;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int i = tid + 256 * k;
+      const int i = tid + NTH * k;
       uint4 v = zero4();
       if (i < NCHUNK) {
         const int pp = i / CH, part = i - pp * CH;
@@ -116,7 +121,7 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles)
     uint4* dst = reinterpret_cast<uint4*>(sIn);
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
-      const int i = tid + 256 * k;
+      const int i = tid + NTH * k;
       if (i < NCHUNK) {
         const int pp = i / CH, part = i - pp * CH;
         dst[pp * (CP / 8) + part] = pre[k];
@@ -139,15 +144,15 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles)
     const int x0 = tx * 16, y0 = ty * 16;
     const int64_t img = (int64_t)b * a.H * a.W;
 
-    f32x4 acc[NCB][4];
+    f32x4 acc[NCB][RPW];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+      for (int rr = 0; rr < RPW; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
 
     // operands of k-step ks (weights: 16 output channels x 32 k; input: 32 k
     // x 16 pixels of one row), read from LDS
-    auto frags = [&](int ks, bf16x8 (&af)[NCB], bf16x8 (&bfr)[4]) {
+    auto frags = [&](int ks, bf16x8 (&af)[NCB], bf16x8 (&bfr)[RPW]) {
       const int k0 = 32 * ks + 8 * g;
       const bool kv = k0 < K;
       const int tap = kv ? k0 / CIN : 0, ci0 = kv ? k0 % CIN : 0;
@@ -156,36 +161,45 @@ __global__ __launch_bounds__(256, 2) void conv3x3_kernel(ConvArgs a, int ntiles)
       for (int cb = 0; cb < NCB; ++cb)
         af[cb] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * KP + k0]) : zero4());
 #pragma unroll
-      for (int rr = 0; rr < 4; ++rr) {
-        const int row = 4 * wave + rr;
+      for (int rr = 0; rr < RPW; ++rr) {
+        const int row = RPW * wave + rr;
         bfr[rr] = as_bf16x8(kv ? *reinterpret_cast<const uint4*>(&sIn[((row + dy) * 18 + j + dx) * CP + ci0]) : zero4());
       }
     };
-    auto mfmas = [&](const bf16x8 (&af)[NCB], const bf16x8 (&bfr)[4]) {
+    auto mfmas = [&](const bf16x8 (&af)[NCB], const bf16x8 (&bfr)[RPW]) {
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
+        for (int rr = 0; rr < RPW; ++rr)
           acc[cb][rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cb], bfr[rr], acc[cb][rr], 0, 0, 0);
     };
-    // two operand sets: the reads of step ks+1 are in flight while the
-    // matrix cores work on step ks (each accumulator still sums the k-steps
-    // in ascending order)
-    bf16x8 a0[NCB], b0[4], a1[NCB], b1[4];
-    frags(0, a0, b0);
-    int ks = 0;
-    for (; ks + 1 < KSTEPS; ks += 2) {
-      frags(ks + 1, a1, b1);
-      mfmas(a0, b0);
-      if (ks + 2 < KSTEPS) frags(ks + 2, a0, b0);
-      mfmas(a1, b1);
+    if constexpr (NW == 4) {
+      // two operand sets: the reads of step ks+1 are in flight while the
+      // matrix cores work on step ks (each accumulator still sums the
+      // k-steps in ascending order)
+      bf16x8 a0[NCB], b0[RPW], a1[NCB], b1[RPW];
+      frags(0, a0, b0);
+      int ks = 0;
+      for (; ks + 1 < KSTEPS; ks += 2) {
+        frags(ks + 1, a1, b1);
+        mfmas(a0, b0);
+        if (ks + 2 < KSTEPS) frags(ks + 2, a0, b0);
+        mfmas(a1, b1);
+      }
+      if (ks < KSTEPS) mfmas(a0, b0);
+    } else {
+      // one operand set: the other waves of the SIMD cover the LDS latency
+      bf16x8 a0[NCB], b0[RPW];
+      for (int ks = 0; ks < KSTEPS; ++ks) {
+        frags(ks, a0, b0);
+        mfmas(a0, b0);
+      }
     }
-    if (ks < KSTEPS) mfmas(a0, b0);
 
     // lane holds D[co = 16 cb + 4 g + r][pixel (row, j)], r = 0..3
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      const int row = 4 * wave + rr;
+    for (int rr = 0; rr < RPW; ++rr) {
+      const int row = RPW * wave + rr;
       const int64_t pix = img + (int64_t)(y0 + row) * a.W + (x0 + j);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
@@ -606,20 +620,27 @@ static int cu_count() {
   return cus;
 }
 
+// Waves per convolution workgroup: 8 (two pixel rows each) run four waves per
+// SIMD in 128 registers; 4 (four rows each) hold more accumulators per wave
+// but only two waves per SIMD.
+constexpr int kConvWaves = 8;
+
 // Persistent grid: as many workgroups as the device holds at once (queried
 // once per kernel), never more than there are tiles.
 template <int CIN, int COUT, int EPI>
 static hipError_t launch_conv(const ConvArgs& a, int ntiles, hipStream_t st) {
+  constexpr int NW = kConvWaves;
   static int per_cu = 0;
   if (per_cu == 0) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&conv3x3_kernel<CIN, COUT, EPI>),
-                                                     256, 0) != hipSuccess || n < 1)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &n, reinterpret_cast<const void*>(&conv3x3_kernel<CIN, COUT, EPI, NW>), 64 * NW, 0) != hipSuccess ||
+        n < 1)
       n = 1;
     per_cu = n;
   }
   const dim3 grid((unsigned)std::min(ntiles, per_cu * cu_count()));
-  hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, EPI>), grid, dim3(256), 0, st, a, ntiles);
+  hipLaunchKernelGGL((conv3x3_kernel<CIN, COUT, EPI, NW>), grid, dim3(64 * NW), 0, st, a, ntiles);
   return hipGetLastError();
 }
 
