@@ -356,11 +356,23 @@ int nlse_surrogate_field_mass(nlse_surrogate *m, const void *psi, int batch,
 int nlse_surrogate_project_msd(nlse_surrogate *m, const void *psi_in,
                                void *psi_out, int batch);
 
+/* One surrogate block on `batch` fields in one pass: psi_out = psi_in +
+ * net(psi_in), with (project_msd != 0) the boundary ring projected as
+ * nlse_surrogate_project_msd does (same bits), and the masses
+ * h^2 sum |psi_out|^2 of the results into the host array mass (batch
+ * doubles).  The last layer does the projection and per-tile FP64 sums of
+ * |psi_out|^2 in its epilogue, and a fixed-order pass adds the tiles of each
+ * field (bitwise reproducible; the summation order differs from
+ * nlse_surrogate_field_mass, so the last bits may).  psi_out must not alias
+ * psi_in.  Synchronises. */
+int nlse_surrogate_block(nlse_surrogate *m, const void *psi_in, void *psi_out,
+                         int batch, int project_msd, double *mass);
+
 /* Advance a 2D FP32 grid (same H x W, same stream) by nblocks blocks of 16
  * RK4 steps of size dt: each block is one surrogate evaluation (plus the MSD
  * projection when bc is NLSE_BC_MSD); if the relative mass drift of the block
  * exceeds drift_tol the block is discarded and recomputed by nlse_step_rk4
- * (order, bc, dt, 16).  *n_fallbacks receives the number of such blocks.
+ * (order, bc, dt, 16).  Each block is one nlse_surrogate_block pass.  *n_fallbacks receives the number of such blocks.
  * Synchronises once or twice per block. */
 int nlse_surrogate_advance(nlse_surrogate *m, nlse_grid *g, int order, int bc,
                            double dt, int64_t nblocks, double drift_tol,

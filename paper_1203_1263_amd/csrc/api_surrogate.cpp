@@ -53,10 +53,12 @@ void layers(Layer L[kNL], int* nparams) {
 }
 
 struct SgLayout {
-  size_t x8, act, pred, dz6, dzA, dzB, scratch, wf[kNL], wb[kNL], grad, m, v, wpart, lpart, mpart, mout, total;
+  size_t x8, act, pred, dz6, dzA, dzB, scratch, wf[kNL], wb[kNL], grad, m, v, wpart, lpart, mpart, mout, tmass,
+      total;
 };
 
 SgLayout layout(int64_t P, int64_t fieldpts, int max_batch) {
+  const int64_t tiles_per_field = fieldpts / 256;  // 16 x 16 pixel tiles
   Layer L[kNL];
   int np;
   layers(L, &np);
@@ -88,6 +90,7 @@ SgLayout layout(int64_t P, int64_t fieldpts, int max_batch) {
   S.lpart = take((size_t)kLossParts * 8);
   S.mpart = take((size_t)max_batch * kMassChunks * 8);
   S.mout = take((size_t)max_batch * 8);
+  S.tmass = take((size_t)max_batch * tiles_per_field * 8);
   S.total = off;
   return S;
 }
@@ -235,8 +238,12 @@ static int check_batch(nlse_surrogate* m, int batch) {
   return NLSE_OK;
 }
 
-// Forward pass of `batch` fields; activations stay in the workspace.
-static hipError_t forward(nlse_surrogate* m, const void* psi_in, void* psi_out, int batch) {
+// Forward pass of `batch` fields; activations stay in the workspace.  With
+// `checked`, the last layer also projects the boundary ring to the input's
+// modulus (project) and sums |psi_out|^2 per tile, and the field masses go to
+// the workspace (mout).
+static hipError_t forward(nlse_surrogate* m, const void* psi_in, void* psi_out, int batch, bool checked = false,
+                          bool project = false) {
   const int64_t P = (int64_t)batch * m->H * m->W;
   hipError_t e = sg_pack_input(psi_in, m->work + m->lay.x8, P, m->stream);
   for (int l = 0; l < kNL && e == hipSuccess; ++l) {
@@ -251,8 +258,15 @@ static hipError_t forward(nlse_surrogate* m, const void* psi_in, void* psi_out, 
     c.B = batch;
     c.H = m->H;
     c.W = m->W;
+    if (l == kNL - 1 && checked) {
+      c.project = project ? 1 : 0;
+      c.tile_mass = F64(m, m->lay.tmass);
+    }
     e = sg_conv(m->L[l].kind, c, m->stream);
   }
+  if (e == hipSuccess && checked)
+    e = sg_tile_mass_final(F64(m, m->lay.tmass), batch, (m->H / 16) * (m->W / 16), m->h * m->h, F64(m, m->lay.mout),
+                           m->stream);
   return e;
 }
 
@@ -355,6 +369,27 @@ static int masses(nlse_surrogate* m, const void* psi, int batch, double* out_hos
   return e == hipSuccess ? NLSE_OK : nlse_hip_fail(e, "field masses");
 }
 
+// The field masses a checked forward pass left in the workspace, to the host.
+static int fetch_masses(nlse_surrogate* m, int batch, double* out_host) {
+  hipError_t e = hipMemcpyAsync(out_host, m->work + m->lay.mout, (size_t)batch * 8, hipMemcpyDeviceToHost, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  return e == hipSuccess ? NLSE_OK : nlse_hip_fail(e, "field masses");
+}
+
+extern "C" int nlse_surrogate_block(nlse_surrogate* m, const void* psi_in, void* psi_out, int batch, int project_msd,
+                                    double* mass) {
+  int rc = check_batch(m, batch);
+  if (rc) return rc;
+  if (!psi_in || !psi_out) return nlse_fail(NLSE_EINVAL, "NULL field");
+  if (psi_in == psi_out) return nlse_fail(NLSE_EINVAL, "psi_in and psi_out must differ");
+  if (!mass) return nlse_fail(NLSE_EINVAL, "mass is NULL");
+  const bool project = project_msd != 0;
+  hipError_t e = replay(m, std::make_tuple(psi_in, psi_out, batch, project ? 4 : 3),
+                        [&]() { return forward(m, psi_in, psi_out, batch, true, project); });
+  if (e != hipSuccess) return nlse_hip_fail(e, "surrogate block");
+  return fetch_masses(m, batch, mass);
+}
+
 extern "C" int nlse_surrogate_field_mass(nlse_surrogate* m, const void* psi, int batch, double* mass) {
   int rc = check_batch(m, batch);
   if (rc) return rc;
@@ -389,18 +424,18 @@ extern "C" int nlse_surrogate_advance(nlse_surrogate* m, nlse_grid* g, int order
   double Min = 0.0;
   int rc = masses(m, psi, 1, &Min);
   if (rc) return rc;
-  // one block: keep its input, predict, project the boundary ring (captured)
+  // one block: keep its input, predict, project the boundary ring and sum
+  // the new field's mass, all in the last layer's pass (captured)
   auto block = [&]() {
     hipError_t e = nlse_launch_copy(xin, psi, (int64_t)bytes, m->stream);
-    if (e == hipSuccess) e = forward(m, xin, psi, 1);
-    if (e == hipSuccess && bc == NLSE_BC_MSD) e = sg_msd_project(xin, psi, 1, m->H, m->W, m->stream);
+    if (e == hipSuccess) e = forward(m, xin, psi, 1, true, bc == NLSE_BC_MSD);
     return e;
   };
   for (int64_t k = 0; k < nblocks; ++k) {
     hipError_t e = replay(m, std::make_tuple((const void*)xin, psi, 1, bc == NLSE_BC_MSD ? 2 : 1), block);
     if (e != hipSuccess) return nlse_hip_fail(e, "surrogate block");
     double Mout = 0.0;
-    if ((rc = masses(m, psi, 1, &Mout))) return rc;
+    if ((rc = fetch_masses(m, 1, &Mout))) return rc;
     const double drift = std::fabs(Mout - Min) / Min;
     if (!(drift <= drift_tol)) {  // also catches NaN
       e = hipMemcpyAsync(psi, xin, bytes, hipMemcpyDeviceToDevice, m->stream);

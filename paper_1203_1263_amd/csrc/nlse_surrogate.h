@@ -16,6 +16,8 @@ struct SgConv {
   void* pred;            // prediction, complex64 (last layer)
   const uint16_t* mask;  // activation gating the gradient (dgrad kinds)
   int B, H, W;
+  int project;           // last layer: MSD projection of the boundary ring
+  double* tile_mass;     // last layer, or null: per 16x16 tile, sum of |pred|^2
 };
 
 hipError_t sg_pack_input(const void* psi, void* x, int64_t n, hipStream_t st);
@@ -33,3 +35,6 @@ hipError_t sg_adam(float* p, const float* g, float* m, float* v, int n, float lr
 hipError_t sg_field_mass(const void* psi, int fields, int64_t n, double h2, double* partial, int chunks, double* out,
                          hipStream_t st);
 hipError_t sg_msd_project(const void* in, void* out, int B, int H, int W, hipStream_t st);
+// out[f] = h2 * (sum of the `tiles` tile sums of field f, in order)
+hipError_t sg_tile_mass_final(const double* tile_mass, int fields, int tiles, double h2, double* out,
+                              hipStream_t st);

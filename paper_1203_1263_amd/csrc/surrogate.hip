@@ -57,6 +57,8 @@ struct ConvArgs {
   float2* pred;          // prediction (last layer)
   const uint16_t* mask;  // dgrad: activation whose sign gates the gradient, [B][H][W][COUT]
   int H, W;
+  int project;           // last layer: MSD projection of the boundary ring
+  double* tile_mass;     // last layer, or null: sum of |pred|^2 of every tile
 };
 
 enum { kEpiRelu = 0, kEpiLast = 1, kEpiDgrad = 2 };
@@ -83,6 +85,7 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, in
   constexpr int NLD = (NCHUNK + NTH - 1) / NTH;
   __shared__ __attribute__((aligned(16))) uint16_t sIn[18 * 18 * CP];
   __shared__ __attribute__((aligned(16))) uint16_t sW[COUT * KP];
+  __shared__ double sMass[NW];
 
   const int tid = threadIdx.x;
   const int tilesx = a.W / 16, tilesy = a.H / 16;
@@ -197,6 +200,7 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, in
     }
 
     // lane holds D[co = 16 cb + 4 g + r][pixel (row, j)], r = 0..3
+    double mass = 0.0;  // last layer: |pred|^2 of this lane's pixels, rows in order
 #pragma unroll
     for (int rr = 0; rr < RPW; ++rr) {
       const int row = RPW * wave + rr;
@@ -218,13 +222,36 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, in
         if constexpr (EPI == kEpiLast) {
           if (g == 0) {  // channels 0, 1 are the real and imaginary increments
             const float2 xv = a.x[pix];
-            a.pred[pix] = make_float2(xv.x + (v[0] + a.bias[0]), xv.y + (v[1] + a.bias[1]));
+            float2 p = make_float2(xv.x + (v[0] + a.bias[0]), xv.y + (v[1] + a.bias[1]));
+            const int py = y0 + row, px = x0 + j;
+            if (a.project && (py == 0 || py == a.H - 1 || px == 0 || px == a.W - 1)) {
+              // the operations of msd_project_kernel, so both give the same bits
+              const float mi = sqrtf(xv.x * xv.x + xv.y * xv.y), mo = sqrtf(p.x * p.x + p.y * p.y);
+              if (mo > 0.f) p = make_float2(p.x * (mi / mo), p.y * (mi / mo));
+            }
+            a.pred[pix] = p;
+            mass += (double)p.x * p.x + (double)p.y * p.y;
           }
         } else {
           uint2 o;
           o.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
           o.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
           *reinterpret_cast<uint2*>(a.out + pix * COUT + co) = o;
+        }
+      }
+    }
+    if constexpr (EPI == kEpiLast) {
+      // tile mass in a fixed order: lanes (a fixed shuffle tree), then the
+      // waves in ascending order
+      if (a.tile_mass) {
+        for (int off = 32; off >= 1; off >>= 1) mass += __shfl_xor(mass, off, 64);
+        if (lane == 0) sMass[wave] = mass;
+        __syncthreads();
+        if (tid == 0) {
+          double t_m = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) t_m += sMass[w];
+          a.tile_mass[t] = t_m;
         }
       }
     }
@@ -568,6 +595,21 @@ __global__ void field_mass_final_kernel(const double* __restrict__ partial, int 
   out[f] = h2 * s;
 }
 
+// Field masses from the last layer's tile sums, one workgroup per field:
+// thread i adds tiles i, i + 256, ... in order, then a fixed tree over the
+// threads (lanes by shuffles, then the four waves in order); h^2 times that.
+__global__ __launch_bounds__(256) void tile_mass_final_kernel(const double* __restrict__ tile_mass, int tiles,
+                                                              double h2, double* __restrict__ out) {
+  __shared__ double red[4];
+  const int f = blockIdx.x;
+  double s = 0.0;
+  for (int c = threadIdx.x; c < tiles; c += 256) s += tile_mass[(int64_t)f * tiles + c];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[f] = h2 * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
 // MSD boundary projection: boundary points of the prediction keep their
 // phase and take the modulus of the input (|psi_b|^2 is the fixed value of
 // the modulus-squared Dirichlet condition, Eq. BCMSDdef).
@@ -661,6 +703,8 @@ hipError_t sg_conv(int kind, const SgConv& c, hipStream_t st) {
   a.mask = c.mask;
   a.H = c.H;
   a.W = c.W;
+  a.project = c.project;
+  a.tile_mass = c.tile_mass;
   const int ntiles = c.B * (c.H / 16) * (c.W / 16);
   switch (kind) {
     case kSgFirst: return launch_conv<8, 48, kEpiRelu>(a, ntiles, st);
@@ -729,6 +773,12 @@ hipError_t sg_field_mass(const void* psi, int fields, int64_t n, double h2, doub
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(field_mass_final_kernel, dim3((fields + 255) / 256), dim3(256), 0, st, partial, fields, chunks,
                      h2, out);
+  return hipGetLastError();
+}
+
+hipError_t sg_tile_mass_final(const double* tile_mass, int fields, int tiles, double h2, double* out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(tile_mass_final_kernel, dim3(fields), dim3(256), 0, st, tile_mass, tiles, h2, out);
   return hipGetLastError();
 }
 

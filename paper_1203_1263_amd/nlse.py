@@ -109,6 +109,7 @@ def load_library() -> ctypes.CDLL:
         "nlse_surrogate_train_step": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_float, dp]),
         "nlse_surrogate_field_mass": (ctypes.c_int, [vp, vp, ctypes.c_int, dp]),
         "nlse_surrogate_project_msd": (ctypes.c_int, [vp, vp, vp, ctypes.c_int]),
+        "nlse_surrogate_block": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int, dp]),
         "nlse_surrogate_advance": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                                   ctypes.c_int64, ctypes.c_double, i64p]),
         "nlse_surrogate_destroy": (ctypes.c_int, [vp]),
@@ -317,6 +318,14 @@ def nlse_surrogate_train_step(m, psi_in_ptr, tgt_ptr, batch, lr, want_loss=True)
 def nlse_surrogate_field_mass(m, psi_ptr, batch):
     out = (ctypes.c_double * batch)()
     _check(load_library().nlse_surrogate_field_mass(m, psi_ptr, batch, out), "nlse_surrogate_field_mass")
+    return list(out)
+
+
+def nlse_surrogate_block(m, psi_in, psi_out, batch: int, project_msd: bool = True):
+    """Forward, MSD projection and masses of one surrogate block in one pass."""
+    out = (ctypes.c_double * batch)()
+    _check(load_library().nlse_surrogate_block(m, psi_in, psi_out, batch, 1 if project_msd else 0, out),
+           "nlse_surrogate_block")
     return list(out)
 
 
@@ -594,6 +603,12 @@ class Surrogate:
     def field_mass(self, psi):
         b = self._check_fields(psi)
         return nlse_surrogate_field_mass(self._m, psi.data_ptr(), b)
+
+    def block(self, psi_in, psi_out, project_msd: bool = True):
+        """One surrogate block (forward, MSD projection, masses) in one pass;
+        returns the masses of psi_out."""
+        b = self._check_fields(psi_in)
+        return nlse_surrogate_block(self._m, psi_in.data_ptr(), psi_out.data_ptr(), b, project_msd)
 
     def project_msd(self, psi_in, psi_out):
         b = self._check_fields(psi_in)

@@ -204,16 +204,15 @@ def _time(fn, reps: int):
 
 
 def speedup(m, snaps, batch: int):
-    """Time of one block: surrogate forward + mass check vs 16 RK4 steps."""
+    """Time of one block (surrogate forward, MSD projection and mass check,
+    one library call) vs 16 RK4 steps."""
     import torch
     dt = dt_default()
     fields = snaps[:batch, 0].contiguous()
     out = torch.empty_like(fields)
 
     def surrogate_block():
-        m.forward(fields, out)
-        m.project_msd(fields, out)
-        m.field_mass(out)   # drift check (synchronises)
+        m.block(fields, out)  # forward, MSD projection and masses in one pass (synchronises)
 
     if batch == 1:
         psi = fields[0].clone()

@@ -49,3 +49,4 @@ hipError_t sg_field_mass(const void*, int, int64_t, double, double*, int, double
   return hipErrorNotSupported;
 }
 hipError_t sg_msd_project(const void*, void*, int, int, int, hipStream_t) { return hipErrorNotSupported; }
+hipError_t sg_tile_mass_final(const double*, int, int, double, double*, hipStream_t) { return hipErrorNotSupported; }

@@ -351,3 +351,27 @@ def test_full_size_gradients_elementwise_and_batch_consistent():
             fails.append(l + 1)
     assert not fails, f"layers {fails}"
     m.close()
+
+
+def test_block_equals_forward_projection_and_mass():
+    """nlse_surrogate_block (projection and masses in the last layer's pass)
+    gives the bits of forward + project_msd, and masses within FP64 rounding
+    of nlse_surrogate_field_mass, at 256^2 batch 3 (several tiles per
+    workgroup) and at batch 1; without projection it equals forward."""
+    import torch
+    H = W = 256
+    m, p, _ = make(H, W, 3, seed=41)
+    for B in (3, 1):
+        x = torch.from_numpy(fields(B, H, W, 42 + B).astype(np.complex64)).cuda()
+        ref = m.forward(x)
+        m.project_msd(x, ref)
+        Mref = m.field_mass(ref)
+        out = torch.empty_like(x)
+        M = m.block(x, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        assert M == pytest.approx(Mref, rel=1e-13)
+        plain = torch.empty_like(x)
+        m.block(x, plain, project_msd=False)
+        assert torch.equal(plain, m.forward(x))
+    m.close()
