@@ -272,13 +272,13 @@ int nlse_batch_mass_energy(nlse_batch *b, double *mass, double *energy);
  * out since creation (the fields are then not valid), else NLSE_OK. */
 int nlse_batch_status(nlse_batch *b);
 
-/* Tile (tx x ty: 32x8, 64x4 or 64x8) and persistent workgroups per CU
+/* Tile (tx x ty: 32x8, 64x4, 64x8, 128x4 or 64x16) and persistent workgroups per CU
  * (1..16; the grid holds min(wg_per_cu, what fits on a CU) x CUs
  * workgroups) of the batched kernel.  Any configuration gives bitwise the
  * same fields as single grids with that tile.  nlse_batch_set_config
  * rebuilds the static schedule for it (synchronises; NLSE_EUNSUPPORTED for
  * a tile that is not compiled).  Created batches use 32x8 and 3 per CU.
- * nlse_batch_autotune times every tile with 2..5 workgroups per CU (up to
+ * nlse_batch_autotune times every tile with 1..5 workgroups per CU (up to
  * what fits) on this batch, running RK4 stages 1-3 only so the fields and
  * the compensation term are not changed, keeps the fastest and stores it in
  * the cache file named by $NLSE_TUNE_CACHE if set (a cached choice for the

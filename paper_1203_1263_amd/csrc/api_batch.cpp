@@ -22,7 +22,7 @@ namespace {
 constexpr int kMaxChunks = 8192;          // upper bound of persistent workgroups
 constexpr unsigned kSpinLimit = 1u << 25; // bounded barrier wait (~1-2 s)
 constexpr int kDefaultWgPerCu = 3;        // persistent workgroups per CU (untuned)
-constexpr int kMinWgPerCu = 2, kMaxWgPerCu = 5;  // the autotuner's range
+constexpr int kMinWgPerCu = 1, kMaxWgPerCu = 5;  // the autotuner's range
 constexpr int64_t kMaxBatchSteps = 1 << 24; // steps per nlse_batch_step_rk4 call
 constexpr size_t kMaxBatchGraphs = 32;    // instantiated graphs kept per batch
 
@@ -54,7 +54,7 @@ int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, in
   if ((flags & NLSE_COMPENSATED) && dtype != NLSE_F32)
     return nlse_fail(NLSE_EUNSUPPORTED, "NLSE_COMPENSATED applies to FP32 only");
   int64_t tot = 0, mb = 1;
-  int64_t items_t[3] = {0, 0, 0};
+  int64_t items_t[nlse::kNumBatchTiles] = {};
   for (int j = 0; j < nsims; ++j) {
     const nlse_sim_desc& d = sims[j];
     if (d.ndim != 2) return nlse_fail(NLSE_EUNSUPPORTED, "problem %d: batches hold 2D problems only", j);
@@ -71,10 +71,11 @@ int validate(int nsims, const nlse_sim_desc* sims, int dtype, unsigned flags, in
     if (d.psi_offset < 0 || d.v_offset < -1) return nlse_fail(NLSE_EINVAL, "problem %d: bad offsets", j);
     const int64_t n = d.dims[0] * d.dims[1];
     tot += n;
-    for (int k = 0; k < 3; ++k) items_t[k] += tiles_of(d, nlse::kBatchTiles[k][0], nlse::kBatchTiles[k][1]);
+    for (int k = 0; k < nlse::kNumBatchTiles; ++k)
+      items_t[k] += tiles_of(d, nlse::kBatchTiles[k][0], nlse::kBatchTiles[k][1]);
     mb = std::max(mb, nlse::reduce_blocks(n));
   }
-  const int64_t items = std::max({items_t[0], items_t[1], items_t[2]});
+  const int64_t items = *std::max_element(items_t, items_t + nlse::kNumBatchTiles);
   if (items > ((int64_t)1 << 31) - 1) return nlse_fail(NLSE_EINVAL, "too many work items");
   *total_pts = tot;
   *nitems = items;

@@ -260,6 +260,8 @@ static const void* kernel_ptr(int tx, int ty) {
   if (tx == 32 && ty == 8) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 32, 8>);
   if (tx == 64 && ty == 4) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 4>);
   if (tx == 64 && ty == 8) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 8>);
+  if (tx == 128 && ty == 4) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 128, 4>);
+  if (tx == 64 && ty == 16) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 16>);
   return nullptr;
 }
 
@@ -288,6 +290,8 @@ static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
   NLSE_LB(32, 8)
   NLSE_LB(64, 4)
   NLSE_LB(64, 8)
+  NLSE_LB(128, 4)
+  NLSE_LB(64, 16)
 #undef NLSE_LB
   return hipErrorInvalidValue;
 }

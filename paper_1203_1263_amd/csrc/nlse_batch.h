@@ -7,9 +7,11 @@
 
 namespace nlse {
 
-// Tiles the batched kernel is compiled for (x-width, y-height); 32 x 8 is
-// the default, the autotuner picks among all three.
-constexpr int kBatchTiles[3][2] = {{32, 8}, {64, 4}, {64, 8}};
+// Tiles the batched kernel is compiled for (x-width, y-height; up to 1024
+// threads, one per point); 32 x 8 is the default, the autotuner picks among
+// all of them.
+constexpr int kNumBatchTiles = 5;
+constexpr int kBatchTiles[kNumBatchTiles][2] = {{32, 8}, {64, 4}, {64, 8}, {128, 4}, {64, 16}};
 
 // One work item (a tile of one problem) as the device sees it: 128 bytes,
 // read by the kernel as 32 dwords, one per lane.  The physical constants are

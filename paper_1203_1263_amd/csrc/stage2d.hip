@@ -29,6 +29,8 @@ struct Launch2D {
     NLSE_L2(32, 8)
     NLSE_L2(64, 4)
     NLSE_L2(64, 8)
+    NLSE_L2(128, 4)
+    NLSE_L2(64, 16)
 #undef NLSE_L2
     return hipErrorInvalidValue;
   }

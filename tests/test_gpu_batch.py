@@ -78,8 +78,9 @@ def test_batch_matches_oracle_and_single_grid(dtype, comp, graph):
     b.close()
 
 
-@pytest.mark.parametrize("tile,wg", [((64, 4), 2), ((64, 8), 4), ((32, 8), 5), ((64, 4), 16)],
-                         ids=["64x4-w2", "64x8-w4", "32x8-w5", "64x4-w16"])
+@pytest.mark.parametrize("tile,wg", [((64, 4), 2), ((64, 8), 4), ((32, 8), 5), ((64, 4), 16), ((128, 4), 2),
+                                     ((64, 16), 1)],
+                         ids=["64x4-w2", "64x8-w4", "32x8-w5", "64x4-w16", "128x4-w2", "64x16-w1"])
 def test_every_tile_and_grid_size_equals_single_grid(tile, wg):
     """Every configuration the autotuner may choose: the batch with tile
     (tx, ty) and wg workgroups per CU is bitwise equal to single grids run
@@ -127,7 +128,7 @@ def test_autotune_keeps_fields_and_caches_its_choice(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(before, b.pool)
     cfg = b.config()
-    assert (cfg[0], cfg[1]) in ((32, 8), (64, 4), (64, 8)) and 2 <= cfg[2] <= 5
+    assert (cfg[0], cfg[1]) in ((32, 8), (64, 4), (64, 8), (128, 4), (64, 16)) and 1 <= cfg[2] <= 5
     b.step(4)
     b.status()
     ref = Batch(probs, dts, compensated=True)
