@@ -257,11 +257,13 @@ int nlse_batch_create(nlse_batch **b, int nsims, const nlse_sim_desc *sims,
 /* Advance every problem nsteps RK4 steps with its own dt (asynchronous, one
  * persistent launch), 0 <= nsteps <= 2^24 (NLSE_EINVAL otherwise, checked
  * first).  Workgroups that share a problem meet at a barrier after every
- * stage, counted in 64-bit arrival counters (the last target of a call,
- * 4 nsteps x group size, cannot wrap); a wait there is bounded (about 2^25 polls, or the
- * value of $NLSE_BATCH_SPIN_LIMIT read at creation), and one that runs out
- * sets an error flag read by nlse_batch_status, after which every waiting
- * workgroup leaves the kernel. */
+ * pass (a stage, or a stage pair), counted in 64-bit arrival counters (the
+ * last target of a call, at most 4 nsteps x group size, cannot wrap); a wait
+ * there is bounded (about 2^25 polls, or the value of $NLSE_BATCH_SPIN_LIMIT
+ * read at creation), and one that runs out sets an error flag read by
+ * nlse_batch_status, after which every waiting workgroup leaves the kernel.
+ * With stage pairs (nlse_batch_set_config) Psi alternates between psi_pool
+ * and the workspace inside a call and is back in psi_pool when it returns. */
 int nlse_batch_step_rk4(nlse_batch *b, int64_t nsteps);
 
 /* Per-problem mass and energy (as nlse_mass_energy, with each problem's own
@@ -272,20 +274,28 @@ int nlse_batch_mass_energy(nlse_batch *b, double *mass, double *energy);
  * out since creation (the fields are then not valid), else NLSE_OK. */
 int nlse_batch_status(nlse_batch *b);
 
-/* Tile (tx x ty: 32x8, 64x4, 64x8, 128x4 or 64x16) and persistent workgroups per CU
- * (1..16; the grid holds min(wg_per_cu, what fits on a CU) x CUs
- * workgroups) of the batched kernel.  Any configuration gives bitwise the
- * same fields as single grids with that tile.  nlse_batch_set_config
- * rebuilds the static schedule for it (synchronises; NLSE_EUNSUPPORTED for
- * a tile that is not compiled).  Created batches use 32x8 and 3 per CU.
- * nlse_batch_autotune times every tile with 1..5 workgroups per CU (up to
- * what fits) on this batch, running RK4 stages 1-3 only so the fields and
- * the compensation term are not changed, keeps the fastest and stores it in
- * the cache file named by $NLSE_TUNE_CACHE if set (a cached choice for the
- * same problem shapes, schemes and boundary conditions is reused without
- * timing).  cfg = {tx, ty, wg_per_cu}. */
-int nlse_batch_set_config(nlse_batch *b, int tx, int ty, int wg_per_cu);
-int nlse_batch_get_config(const nlse_batch *b, int cfg[3]);
+/* Tile (tx x ty: 32x8, 64x4, 64x8, 128x4 or 64x16), persistent workgroups
+ * per CU (1..16; the grid holds min(wg_per_cu, what fits on a CU) x CUs
+ * workgroups) and pass structure of the batched kernel: pairs = 0 runs the
+ * four RK4 stages as four passes over the batch, pairs = 1 as two passes of
+ * two stages (1+2, 3+4; each tile evaluates the first stage of a pair on
+ * itself and the halo ring the second stage reads, so the intermediate
+ * stage never goes through memory; with an odd nsteps the first step of a
+ * call takes three passes).  Any configuration gives bitwise the same
+ * fields as single grids with that tile.  nlse_batch_set_config rebuilds
+ * the static schedule for it (synchronises; NLSE_EUNSUPPORTED for a tile
+ * that is not compiled, NLSE_EINVAL for pairs other than 0 or 1).  Created
+ * batches use 32x8, 3 per CU, pairs = 0.  nlse_batch_autotune times whole
+ * RK4 steps of every tile with 1..5 workgroups per CU (up to what fits) and
+ * pairs 0 and 1 on this batch; it saves Psi and the compensation term to a
+ * temporary device allocation of (1 or 2) x total points x element size
+ * first and restores them afterwards, so the fields are not changed.  It
+ * keeps the fastest and stores it in the cache file named by
+ * $NLSE_TUNE_CACHE if set (a cached choice for the same problem shapes,
+ * schemes and boundary conditions is reused without timing).
+ * cfg = {tx, ty, wg_per_cu, pairs}. */
+int nlse_batch_set_config(nlse_batch *b, int tx, int ty, int wg_per_cu, int pairs);
+int nlse_batch_get_config(const nlse_batch *b, int cfg[4]);
 int nlse_batch_autotune(nlse_batch *b);
 
 /* info[0..3] = workgroups of the persistent launch, work items, total grid

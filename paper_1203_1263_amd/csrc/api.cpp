@@ -724,9 +724,9 @@ static std::string cache_key(const nlse_grid* g, int order, int bc) {
   return buf;
 }
 
-bool nlse_cache_lookup(const std::string& key, int t[3]) {
+bool nlse_cache_lookup(const std::string& key, int* t, int n) {
   const char* path = getenv("NLSE_TUNE_CACHE");
-  if (!path || !*path) return false;
+  if (!path || !*path || n < 1 || n > 8) return false;
   FILE* f = fopen(path, "r");
   if (!f) return false;
   char line[256];
@@ -735,18 +735,33 @@ bool nlse_cache_lookup(const std::string& key, int t[3]) {
     char* bar = strchr(line, '|');
     if (!bar) continue;
     *bar = 0;
-    if (key == line && sscanf(bar + 1, "%d %d %d", &t[0], &t[1], &t[2]) == 3) found = true;
+    if (key != line) continue;
+    int v[8], k = 0;
+    const char* p = bar + 1;
+    for (; k < n; ++k) {
+      char* end = nullptr;
+      const long x = strtol(p, &end, 10);
+      if (end == p) break;
+      v[k] = (int)x;
+      p = end;
+    }
+    if (k == n) {
+      for (int i = 0; i < n; ++i) t[i] = v[i];
+      found = true;
+    }
   }
   fclose(f);
   return found;
 }
 
-void nlse_cache_store(const std::string& key, const int t[3], float ms) {
+void nlse_cache_store(const std::string& key, const int* t, int n, float ms) {
   const char* path = getenv("NLSE_TUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "%s|%d %d %d %.6f\n", key.c_str(), t[0], t[1], t[2], ms);
+  fprintf(f, "%s|", key.c_str());
+  for (int i = 0; i < n; ++i) fprintf(f, "%d ", t[i]);
+  fprintf(f, "%.6f\n", ms);
   fclose(f);
 }
 
@@ -760,7 +775,7 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
   const std::string key = cache_key(g, order, bc);
   int cached[3];
-  if (nlse_cache_lookup(key, cached) && tile_fits(g, order, cached)) {
+  if (nlse_cache_lookup(key, cached, 3) && tile_fits(g, order, cached)) {
     memcpy(g->tile[tile_slot(order)], cached, sizeof cached);
     return NLSE_OK;
   }
@@ -834,6 +849,6 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "autotune launch");
   memcpy(g->tile[tile_slot(order)], best_t.data(), 3 * sizeof(int));
-  nlse_cache_store(key, best_t.data(), best / reps);
+  nlse_cache_store(key, best_t.data(), 3, best / reps);
   return NLSE_OK;
 }

@@ -113,6 +113,7 @@ struct nlse_batch {
   int64_t total_pts, nitems;  // nitems: of the configured tile
   int nchunks, ngroups;
   int tx, ty, wg_per_cu;  // tile and persistent workgroups per CU
+  int pairs;              // 1: two stage-pair passes per step
   int cus;
   unsigned spin_limit;
   void* psi;
@@ -134,8 +135,22 @@ extern "C" int nlse_batch_workspace_bytes(int nsims, const nlse_sim_desc* sims, 
   return NLSE_OK;
 }
 
-static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st, int stages = 4) {
-  // reset the group arrival counters; the error flag before them stays sticky
+// One persistent launch of nsteps steps (preceded by the reset of the group
+// arrival counters; the error flag before them stays sticky).  The stage-pair
+// kernel runs even step counts, so an odd count under pairs starts with one
+// step of the single-stage kernel.
+static hipError_t launch(nlse_batch* b, int64_t nsteps, int pairs, hipStream_t st);
+
+static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st) {
+  if (b->pairs && (nsteps & 1)) {
+    hipError_t e = launch(b, 1, 0, st);
+    if (e != hipSuccess || nsteps == 1) return e;
+    return launch(b, nsteps - 1, 1, st);
+  }
+  return launch(b, nsteps, b->pairs, st);
+}
+
+static hipError_t launch(nlse_batch* b, int64_t nsteps, int pairs, hipStream_t st) {
   hipError_t e = nlse_launch_fill_zero(b->work + b->lay.barrier + 8, 8 * (int64_t)b->ngroups, st);
   if (e != hipSuccess) return e;
   nlse::BatchLaunch L;
@@ -145,7 +160,7 @@ static hipError_t enqueue(nlse_batch* b, int64_t nsteps, hipStream_t st, int sta
   L.nchunks = b->nchunks;
   L.tx = b->tx;
   L.ty = b->ty;
-  L.stages = stages;
+  L.pairs = pairs;
   L.items = reinterpret_cast<const nlse::BatchItem*>(b->work + b->lay.items);
   L.chunk_off = reinterpret_cast<const int*>(b->work + b->lay.chunks);
   L.psi = b->psi;
@@ -306,16 +321,23 @@ extern "C" int nlse_internal_batch_limits(int64_t out[3]) {
   return NLSE_OK;
 }
 
-// Tile, workgroups per CU and the static schedule of a batch: the
-// persistent grid is min(wg_per_cu, what fits) x CUs workgroups; the work
-// items and chunk table are rebuilt and uploaded, and captured graphs (which
-// hold the grid size and tile) are dropped.  Synchronises the stream.
-static int configure(nlse_batch* b, int tx, int ty, int wg_per_cu) {
+// Tile, workgroups per CU, pass structure and the static schedule of a
+// batch: the persistent grid is min(wg_per_cu, what fits) x CUs workgroups;
+// the work items and chunk table are rebuilt and uploaded, and captured
+// graphs (which hold the grid size, tile and kernel) are dropped.
+// Synchronises the stream.
+static int configure(nlse_batch* b, int tx, int ty, int wg_per_cu, int pairs) {
   if (!tile_compiled(tx, ty)) return nlse_fail(NLSE_EUNSUPPORTED, "tile %dx%d is not compiled", tx, ty);
   if (wg_per_cu < 1 || wg_per_cu > 16) return nlse_fail(NLSE_EINVAL, "wg_per_cu must be 1..16");
-  int occ = 0;
-  hipError_t e = nlse_batch_occupancy(b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, tx, ty, &occ);
+  if (pairs != 0 && pairs != 1) return nlse_fail(NLSE_EINVAL, "pairs must be 0 or 1");
+  // the grid must be resident at once for every kernel it runs (with pairs,
+  // an odd step count also runs the single-stage kernel on it)
+  int occ = 0, occ1 = 0;
+  const int comp = (b->flags & NLSE_COMPENSATED) ? 1 : 0;
+  hipError_t e = nlse_batch_occupancy(b->dtype, comp, tx, ty, pairs, &occ);
+  if (e == hipSuccess && pairs) e = nlse_batch_occupancy(b->dtype, comp, tx, ty, 0, &occ1);
   if (e != hipSuccess) return nlse_hip_fail(e, "querying occupancy");
+  if (pairs) occ = std::min(occ, occ1);
   if (occ < 1) return nlse_fail(NLSE_EDEVICE, "the batched kernel does not fit on a CU");
   int64_t items = 0;
   for (const auto& d : b->desc) items += tiles_of(d, tx, ty);
@@ -337,6 +359,7 @@ static int configure(nlse_batch* b, int tx, int ty, int wg_per_cu) {
   b->tx = tx;
   b->ty = ty;
   b->wg_per_cu = wg_per_cu;
+  b->pairs = pairs;
   b->nchunks = (int)nchunks;
   b->ngroups = ngroups;
   b->nitems = items;
@@ -401,7 +424,7 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
     delete B;
     return nlse_hip_fail(e, "creating the batch");
   }
-  rc = configure(B, 32, 8, kDefaultWgPerCu);
+  rc = configure(B, 32, 8, kDefaultWgPerCu, 0);
   if (rc) {
     if (B->cap) (void)hipStreamDestroy(B->cap);
     delete B;
@@ -411,16 +434,17 @@ extern "C" int nlse_batch_create(nlse_batch** out, int nsims, const nlse_sim_des
   return NLSE_OK;
 }
 
-extern "C" int nlse_batch_set_config(nlse_batch* b, int tx, int ty, int wg_per_cu) {
+extern "C" int nlse_batch_set_config(nlse_batch* b, int tx, int ty, int wg_per_cu, int pairs) {
   if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
-  return configure(b, tx, ty, wg_per_cu);
+  return configure(b, tx, ty, wg_per_cu, pairs);
 }
 
-extern "C" int nlse_batch_get_config(const nlse_batch* b, int cfg[3]) {
+extern "C" int nlse_batch_get_config(const nlse_batch* b, int cfg[4]) {
   if (!b || !cfg) return nlse_fail(NLSE_EINVAL, "NULL argument");
   cfg[0] = b->tx;
   cfg[1] = b->ty;
   cfg[2] = b->wg_per_cu;
+  cfg[3] = b->pairs;
   return NLSE_OK;
 }
 
@@ -442,59 +466,92 @@ static std::string batch_key(const nlse_batch* b) {
     mix(d.v_offset >= 0 ? 1 : 0);
   }
   char buf[128];
-  snprintf(buf, sizeof buf, "batch t%d c%d n%d h%016llx", b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, b->nsims,
+  snprintf(buf, sizeof buf, "batch4 t%d c%d n%d h%016llx", b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, b->nsims,
            (unsigned long long)h);
   return buf;
 }
 
-// Times stages 1-3 only (they never write Psi or the compensation term), so
-// the fields are left untouched; the accumulator and stage buffers are
-// scratch.  Every candidate runs the whole batch with its own schedule.
+// Copies every problem's Psi (packed by work offset) and the compensation
+// term between the batch and `save` (to = true: into save).
+static hipError_t copy_fields(nlse_batch* b, char* save, bool to) {
+  const size_t esz = b->dtype == NLSE_F32 ? 8 : 16;
+  size_t woff = 0;
+  hipError_t e = hipSuccess;
+  for (const auto& d : b->desc) {
+    const size_t n = (size_t)(d.dims[0] * d.dims[1]);
+    char* p = static_cast<char*>(b->psi) + (size_t)d.psi_offset * esz;
+    char* q = save + woff * esz;
+    e = hipMemcpyAsync(to ? q : p, to ? p : q, n * esz, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return e;
+    woff += n;
+  }
+  if (b->flags & NLSE_COMPENSATED) {
+    char* lo = b->work + b->lay.lo;
+    char* q = save + (size_t)b->total_pts * esz;
+    e = hipMemcpyAsync(to ? q : lo, to ? lo : q, (size_t)b->total_pts * esz, hipMemcpyDeviceToDevice, b->stream);
+  }
+  return e;
+}
+
+// Times whole RK4 steps of every candidate (tile x workgroups per CU x
+// single-stage / stage-pair passes) on the batch itself, each with its own
+// schedule; Psi and the compensation term are saved to a temporary device
+// buffer first and restored afterwards, so the fields end as they began.
 extern "C" int nlse_batch_autotune(nlse_batch* b) {
   if (!b) return nlse_fail(NLSE_EINVAL, "b is NULL");
   const std::string key = batch_key(b);
-  int cached[3];
-  if (nlse_cache_lookup(key, cached) && tile_compiled(cached[0], cached[1]) && cached[2] >= 1 && cached[2] <= 16)
-    return configure(b, cached[0], cached[1], cached[2]);
+  int cached[4];
+  if (nlse_cache_lookup(key, cached, 4) && tile_compiled(cached[0], cached[1]) && cached[2] >= 1 &&
+      cached[2] <= 16 && (cached[3] == 0 || cached[3] == 1))
+    return configure(b, cached[0], cached[1], cached[2], cached[3]);
+  const size_t esz = b->dtype == NLSE_F32 ? 8 : 16;
+  const size_t save_bytes = (size_t)b->total_pts * esz * ((b->flags & NLSE_COMPENSATED) ? 2 : 1);
+  char* save = nullptr;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(&save), save_bytes);
+  if (e != hipSuccess) return nlse_hip_fail(e, "allocating the autotuner's copy of the fields");
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipEventCreate(&e0);
+  e = copy_fields(b, save, true);
+  if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  if (e != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return nlse_hip_fail(e, "hipEventCreate");
-  }
   const int reps = (int)std::max<int64_t>(2, std::min<int64_t>(50, (int64_t)3e8 / std::max<int64_t>(b->total_pts, 1)));
   float best = 1e30f;
-  int best_c[3] = {32, 8, kDefaultWgPerCu};
+  int best_c[4] = {32, 8, kDefaultWgPerCu, 0};
   int rc = NLSE_OK;
-  for (const auto& t : nlse::kBatchTiles) {
-    int occ = 0;
-    e = nlse_batch_occupancy(b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, t[0], t[1], &occ);
-    if (e != hipSuccess) break;
-    for (int w = kMinWgPerCu; w <= std::min(kMaxWgPerCu, occ); ++w) {
-      if ((rc = configure(b, t[0], t[1], w)) != NLSE_OK) break;
-      if ((e = enqueue(b, 1, b->stream, 3)) != hipSuccess) break;  // warm-up
-      (void)hipEventRecord(e0, b->stream);
-      if ((e = enqueue(b, reps, b->stream, 3)) != hipSuccess) break;
-      (void)hipEventRecord(e1, b->stream);
-      if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
-      if (ms < best) {
-        best = ms;
-        best_c[0] = t[0];
-        best_c[1] = t[1];
-        best_c[2] = w;
+  for (int pairs = 0; pairs <= 1 && e == hipSuccess && rc == NLSE_OK; ++pairs)
+    for (const auto& t : nlse::kBatchTiles) {
+      int occ = 0;
+      e = nlse_batch_occupancy(b->dtype, (b->flags & NLSE_COMPENSATED) ? 1 : 0, t[0], t[1], pairs, &occ);
+      if (e != hipSuccess) break;
+      for (int w = kMinWgPerCu; w <= std::min(kMaxWgPerCu, occ); ++w) {
+        if ((rc = configure(b, t[0], t[1], w, pairs)) != NLSE_OK) break;
+        if ((e = enqueue(b, 2, b->stream)) != hipSuccess) break;  // warm-up
+        (void)hipEventRecord(e0, b->stream);
+        if ((e = enqueue(b, reps, b->stream)) != hipSuccess) break;
+        (void)hipEventRecord(e1, b->stream);
+        if ((e = hipEventSynchronize(e1)) != hipSuccess) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          best_c[0] = t[0];
+          best_c[1] = t[1];
+          best_c[2] = w;
+          best_c[3] = pairs;
+        }
       }
+      if (rc != NLSE_OK || e != hipSuccess) break;
     }
-    if (rc != NLSE_OK || e != hipSuccess) break;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  // restore the fields whatever happened above
+  hipError_t er = copy_fields(b, save, false);
+  if (er == hipSuccess) er = hipStreamSynchronize(b->stream);
+  (void)hipFree(save);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   if (rc != NLSE_OK) return rc;
   if (e != hipSuccess) return nlse_hip_fail(e, "batch autotune launch");
-  rc = configure(b, best_c[0], best_c[1], best_c[2]);
-  if (rc == NLSE_OK) nlse_cache_store(key, best_c, best * 4.0f / 3.0f / reps);
+  if (er != hipSuccess) return nlse_hip_fail(er, "restoring the fields after autotuning");
+  rc = configure(b, best_c[0], best_c[1], best_c[2], best_c[3]);
+  if (rc == NLSE_OK) nlse_cache_store(key, best_c, 4, best / reps);
   return rc;
 }
 

@@ -150,59 +150,72 @@ __device__ __forceinline__ ItemArgs<T> decode(const BatchArgs<T>& B, unsigned w)
   I.ty = word_i32(w, NLSE_WORD(ty));
   return I;
 }
-#undef NLSE_WORD
 
-template <typename T, int TX, int TY>
-struct BatchLds {
-  static constexpr int BSZ = (TX + 4) * (TY + 4);
-  cpx<T> u[2][BSZ];  // stage-input box, alternating between items
-  T v[2][BSZ];       // potential box, alternating between items
-  cpx<T> d[(TX + 2) * (TY + 2)];
+// Arguments of one item of a stage pair, from its descriptor words.  Psi of
+// the step lives in the caller's pool or, on alternate steps, in bufA
+// (src_a); the second pair writes the new Psi to the other one (dst_a).
+template <typename T>
+struct PairItem {
+  PairArgs<T> A;
+  int order, bc, tx, ty;
 };
 
-// One stage over the items [i0, i1) of this workgroup's chunk.
-template <typename T, int STAGE, int COMP, int TX, int TY>
-__device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i1, BatchLds<T, TX, TY>& S) {
-  using Regs = TileRegs<T, TX, TY>;
-  auto words = [&](int it) { return item_words(B.items, min(it, i1 - 1)); };
-  auto issue = [&](const ItemArgs<T>& I, Regs& r) {
-    if (I.order == 4)
-      tile2d_load<T, STAGE, COMP, TX, TY, 2, true>(I.A, I.tx, I.ty, r);
-    else
-      tile2d_load<T, STAGE, COMP, TX, TY, 1, true>(I.A, I.tx, I.ty, r);
-  };
-  auto compute = [&](const ItemArgs<T>& I, const Regs& r, int buf) {
-    cpx<T>* sU = S.u[buf];
-    T* sV = S.v[buf];
-    if (I.order == 4) {
-      if (I.bc == kMSD)
-        tile2d_compute<T, 4, kMSD, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
-      else if (I.bc == kL0)
-        tile2d_compute<T, 4, kL0, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
-      else
-        tile2d_compute<T, 4, kDirichlet, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
-    } else {
-      if (I.bc == kMSD)
-        tile2d_compute<T, 2, kMSD, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
-      else if (I.bc == kL0)
-        tile2d_compute<T, 2, kL0, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
-      else
-        tile2d_compute<T, 2, kDirichlet, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d);
-    }
-  };
-  // Item `it`: its loads are in flight in `cur`, its descriptor words (long
-  // arrived) are in `wc`, the words of item it+1 are in flight in `wn`.
-  // Decode both items, reuse `wc` for the words of item it+2, start the
-  // loads of item it+1 into `nxt`, then compute item it.  The next item
-  // swaps the roles of (wc, wn) and (cur, nxt), so no register that a load
-  // is still writing is ever copied.  The scheduling barrier keeps the
-  // descriptor load ahead of the tile loads: waiting for it later must not
-  // mean waiting for them.  Past the end of the chunk the last item is
-  // loaded again (and not computed), which keeps the memory operations
-  // straight-line code.
+template <typename T, int PAIR>
+__device__ __forceinline__ PairItem<T> decode_pair(const BatchArgs<T>& B, unsigned w, bool src_a, bool dst_a) {
+  PairItem<T> I;
+  PairArgs<T>& A = I.A;
+  const int64_t psi_off = word_i64(w, NLSE_WORD(psi_off)), v_off = word_i64(w, NLSE_WORD(v_off));
+  const int64_t woff = word_i64(w, NLSE_WORD(woff));
+  cpx<T>* psi_src = src_a ? B.bufA + woff : B.psi + psi_off;
+  cpx<T>* u2 = B.bufB + woff;
+  A.uin = PAIR == 1 ? psi_src : u2;
+  A.psi = psi_src;
+  A.acc = B.acc + woff;
+  A.out = PAIR == 1 ? u2 : (dst_a ? B.bufA + woff : B.psi + psi_off);
+  A.lo = B.lo ? B.lo + woff : nullptr;
+  A.V = v_off >= 0 ? B.vpool + v_off : B.vzero;
+  A.vs = v_off >= 0 ? 1 : 0;
+  A.nx = word_i32(w, NLSE_WORD(nx));
+  A.ny = word_i32(w, NLSE_WORD(ny));
+  A.ph.a = (T)word_f64(w, NLSE_WORD(a));
+  A.ph.s = (T)word_f64(w, NLSE_WORD(s));
+  A.ph.inv_a = (T)word_f64(w, NLSE_WORD(inv_a));
+  A.ph.inv_h2 = (T)word_f64(w, NLSE_WORD(inv_h2));
+  A.ph.inv_6h2 = (T)word_f64(w, NLSE_WORD(inv_6h2));
+  const double dt = word_f64(w, NLSE_WORD(dt)), dt2 = word_f64(w, NLSE_WORD(dt2));
+  const double dt3 = word_f64(w, NLSE_WORD(dt3)), dt6 = word_f64(w, NLSE_WORD(dt6));
+  // the coefficients of stages 1, 2 (PAIR 1) or 3, 4 (PAIR 2) as decode gives them
+  A.ca1 = (T)(PAIR == 1 ? dt6 : dt3);
+  A.cn1 = (T)(PAIR == 1 ? dt2 : dt);
+  A.ca2 = (T)(PAIR == 1 ? dt3 : dt6);
+  A.cn2 = (T)dt2;  // stage 2; stage 4 has none
+  A.ca2_d = PAIR == 1 ? dt3 : dt6;
+  I.order = word_i32(w, NLSE_WORD(order));
+  I.bc = word_i32(w, NLSE_WORD(bc));
+  I.tx = word_i32(w, NLSE_WORD(tx));
+  I.ty = word_i32(w, NLSE_WORD(ty));
+  return I;
+}
+#undef NLSE_WORD
+
+// The items [i0, i1) of a chunk, software-pipelined.  Item `it`: its loads
+// are in flight in `cur`, its descriptor words (long arrived) are in `wc`,
+// the words of item it+1 are in flight in `wn`.  Decode both items, reuse
+// `wc` for the words of item it+2, start the loads of item it+1 into `nxt`,
+// then compute item it.  The next item swaps the roles of (wc, wn) and
+// (cur, nxt), so no register that a load is still writing is ever copied.
+// The scheduling barrier keeps the descriptor load ahead of the tile loads:
+// waiting for it later must not mean waiting for them.  Past the end of the
+// chunk the last item is loaded again (and not computed), which keeps the
+// memory operations straight-line code.  `compute` gets the LDS buffer
+// parity of the item (consecutive items alternate).
+template <typename Regs, typename Dec, typename Issue, typename Compute>
+__device__ __forceinline__ void run_items(const BatchItem* items, int i0, int i1, Dec dec, Issue issue,
+                                          Compute compute) {
+  auto words = [&](int it) { return item_words(items, min(it, i1 - 1)); };
   auto body = [&](int it, const Regs& cur, Regs& nxt, unsigned& wc, unsigned wn, int buf) {
-    const ItemArgs<T> Icur = decode<T, STAGE>(B, wc);
-    const ItemArgs<T> Inxt = decode<T, STAGE>(B, wn);
+    const auto Icur = dec(wc);
+    const auto Inxt = dec(wn);
     wc = words(it + 2);
     __builtin_amdgcn_sched_barrier(0);
     issue(Inxt, nxt);
@@ -211,7 +224,7 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
   if (i0 >= i1) return;
   unsigned wa = words(i0), wb = words(i0 + 1);
   Regs ra, rb;
-  const ItemArgs<T> I0 = decode<T, STAGE>(B, wa);
+  const auto I0 = dec(wa);
   __builtin_amdgcn_sched_barrier(0);
   issue(I0, ra);
   int it = i0;
@@ -222,52 +235,158 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
   if (it < i1) body(it, ra, rb, wa, wb, 0);
 }
 
-template <typename T, int COMP, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void batch2d_kernel(BatchArgs<T> B, int nsteps, int stages) {
-  __shared__ BatchLds<T, TX, TY> S;
-  const int c = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int i0 = B.chunk_off[c], i1 = B.chunk_off[c + 1];
-  const int* meta = B.chunk_off + gridDim.x + 1 + 4 * c;
-  const int ga = meta[0], gb = meta[2];
-  const unsigned sa = (unsigned)meta[1], sb = (unsigned)meta[3];
-  unsigned long long k = 0;
-  // a chunk whose problems all lie inside it reads only its own earlier
-  // stores: a workgroup barrier orders them
-  auto sync = [&]() -> bool {
+template <typename T, int TX, int TY>
+struct BatchLds {
+  static constexpr int BSZ = (TX + 4) * (TY + 4);
+  cpx<T> u[2][BSZ];  // stage-input box, alternating between items
+  T v[2][BSZ];       // potential box, alternating between items
+  cpx<T> d[(TX + 2) * (TY + 2)];
+};
+
+// LDS of a stage pair: input and potential box with the 2SHOC pair halo of
+// 4 (alternating between items), the first stage's D box (the second
+// stage's D is smaller and reuses it) and the first stage's output on the
+// tile and its ring of 2.
+template <typename T, int TX, int TY>
+struct PairLds {
+  static constexpr int BSZ = (TX + 8) * (TY + 8);
+  cpx<T> u[2][BSZ];
+  T v[2][BSZ];
+  cpx<T> d[(TX + 6) * (TY + 6)];
+  cpx<T> m[(TX + 4) * (TY + 4)];
+};
+
+// One stage over the items [i0, i1) of this workgroup's chunk.
+template <typename T, int STAGE, int COMP, int TX, int TY>
+__device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i1, BatchLds<T, TX, TY>& S) {
+  using Regs = TileRegs<T, TX, TY>;
+  auto dec = [&](unsigned w) { return decode<T, STAGE>(B, w); };
+  auto issue = [&](const ItemArgs<T>& I, Regs& r) {
+    if (I.order == 4)
+      tile2d_load<T, STAGE, COMP, TX, TY, 2, true>(I.A, I.tx, I.ty, r);
+    else
+      tile2d_load<T, STAGE, COMP, TX, TY, 1, true>(I.A, I.tx, I.ty, r);
+  };
+  auto compute = [&](const ItemArgs<T>& I, const Regs& r, int buf) {
+    cpx<T>* sU = S.u[buf];
+    T* sV = S.v[buf];
+    if (I.order == 4)
+      tile2d_compute<T, 4, kAnyBC, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d, I.bc);
+    else
+      tile2d_compute<T, 2, kAnyBC, STAGE, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d, I.bc);
+  };
+  run_items<Regs>(B.items, i0, i1, dec, issue, compute);
+}
+
+// One stage pair (PAIR 1: stages 1+2, PAIR 2: stages 3+4) over the items
+// [i0, i1) of this workgroup's chunk.
+template <typename T, int PAIR, int COMP, int TX, int TY>
+__device__ __forceinline__ void batch_pair(const BatchArgs<T>& B, int i0, int i1, PairLds<T, TX, TY>& S, bool src_a,
+                                           bool dst_a) {
+  using Regs = PairRegs<T, TX, TY>;
+  auto dec = [&](unsigned w) { return decode_pair<T, PAIR>(B, w, src_a, dst_a); };
+  auto issue = [&](const PairItem<T>& I, Regs& r) {
+    if (I.order == 4)
+      pair2d_load<T, PAIR, COMP, TX, TY, 2, true>(I.A, I.tx, I.ty, r);
+    else
+      pair2d_load<T, PAIR, COMP, TX, TY, 1, true>(I.A, I.tx, I.ty, r);
+  };
+  auto compute = [&](const PairItem<T>& I, const Regs& r, int buf) {
+    cpx<T>* sU = S.u[buf];
+    T* sV = S.v[buf];
+    if (I.order == 4)
+      pair2d_compute<T, 4, kAnyBC, PAIR, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d, S.m, I.bc);
+    else
+      pair2d_compute<T, 2, kAnyBC, PAIR, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d, S.m, I.bc);
+  };
+  run_items<Regs>(B.items, i0, i1, dec, issue, compute);
+}
+
+// The chunk of this workgroup and its barrier between passes: a chunk whose
+// problems all lie inside it reads only its own earlier stores (a workgroup
+// barrier orders them); otherwise it meets its groups.
+struct ChunkSync {
+  int i0, i1, ga, gb;
+  unsigned sa, sb;
+  unsigned long long k;
+  template <typename T>
+  __device__ __forceinline__ ChunkSync(const BatchArgs<T>& B) : k(0) {
+    const int c = xcd_swizzle(blockIdx.x, gridDim.x);
+    i0 = B.chunk_off[c];
+    i1 = B.chunk_off[c + 1];
+    const int* meta = B.chunk_off + gridDim.x + 1 + 4 * c;
+    ga = meta[0];
+    gb = meta[2];
+    sa = (unsigned)meta[1];
+    sb = (unsigned)meta[3];
+  }
+  template <typename T>
+  __device__ __forceinline__ bool operator()(const BatchArgs<T>& B) {
     if (ga < 0 && gb < 0) {
       __syncthreads();
       return true;
     }
     return group_barrier(B.flag, B.arrivals, ga, sa, gb, sb, ++k, B.spin_limit);
-  };
-  // stages == 3 (timing only) stops before the stage that writes Psi
+  }
+};
+
+// nsteps RK4 steps, four single-stage passes each.
+template <typename T, int COMP, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void batch2d_kernel(BatchArgs<T> B, int nsteps) {
+  __shared__ BatchLds<T, TX, TY> S;
+  ChunkSync sync(B);
+  const int i0 = sync.i0, i1 = sync.i1;
   for (int n = 0; n < nsteps; ++n) {
     batch_stage<T, 1, COMP, TX, TY>(B, i0, i1, S);
-    if (!sync()) return;
+    if (!sync(B)) return;
     batch_stage<T, 2, COMP, TX, TY>(B, i0, i1, S);
-    if (!sync()) return;
+    if (!sync(B)) return;
     batch_stage<T, 3, COMP, TX, TY>(B, i0, i1, S);
-    if (!sync()) return;
-    if (stages == 4) {
-      batch_stage<T, 4, COMP, TX, TY>(B, i0, i1, S);
-      if (!sync()) return;
-    }
+    if (!sync(B)) return;
+    batch_stage<T, 4, COMP, TX, TY>(B, i0, i1, S);
+    if (!sync(B)) return;
+  }
+}
+
+// nsteps RK4 steps (nsteps even), two stage-pair passes each.  The second
+// pass reads Psi on its tiles' rings, which neighbouring tiles are
+// overwriting in the same pass, so the new Psi goes to the other of
+// (caller's pool, bufA): odd steps read bufA and write the caller's pool,
+// even steps the reverse, so the last step ends in the caller's pool.  (An
+// odd step count starts with one step of batch2d_kernel, whose stage 4
+// reads Psi at its own points only and writes it in place.)
+template <typename T, int COMP, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void batch2d_pair_kernel(BatchArgs<T> B, int nsteps) {
+  __shared__ PairLds<T, TX, TY> S;
+  ChunkSync sync(B);
+  const int i0 = sync.i0, i1 = sync.i1;
+  for (int n = 0; n < nsteps; ++n) {
+    const bool odd = n & 1;
+    batch_pair<T, 1, COMP, TX, TY>(B, i0, i1, S, odd, !odd);
+    if (!sync(B)) return;
+    batch_pair<T, 2, COMP, TX, TY>(B, i0, i1, S, odd, !odd);
+    if (!sync(B)) return;
   }
 }
 
 template <typename T, int COMP>
-static const void* kernel_ptr(int tx, int ty) {
-  if (tx == 32 && ty == 8) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 32, 8>);
-  if (tx == 64 && ty == 4) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 4>);
-  if (tx == 64 && ty == 8) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 8>);
-  if (tx == 128 && ty == 4) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 128, 4>);
-  if (tx == 64 && ty == 16) return reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, 64, 16>);
+static const void* kernel_ptr(int tx, int ty, int pairs) {
+#define NLSE_KP(TX_, TY_)                                                                       \
+  if (tx == TX_ && ty == TY_)                                                                   \
+    return pairs ? reinterpret_cast<const void*>(&batch2d_pair_kernel<T, COMP, TX_, TY_>)       \
+                 : reinterpret_cast<const void*>(&batch2d_kernel<T, COMP, TX_, TY_>);
+  NLSE_KP(32, 8)
+  NLSE_KP(64, 4)
+  NLSE_KP(64, 8)
+  NLSE_KP(128, 4)
+  NLSE_KP(64, 16)
+#undef NLSE_KP
   return nullptr;
 }
 
 template <typename T, int COMP>
 static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
-  if (L.stages != 3 && L.stages != 4) return hipErrorInvalidValue;
+  if (L.pairs && (L.nsteps & 1)) return hipErrorInvalidValue;  // the pair kernel runs even step counts
   BatchArgs<T> B;
   B.items = L.items;
   B.chunk_off = L.chunk_off;
@@ -281,11 +400,14 @@ static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
   B.flag = L.barrier + 1;
   B.arrivals = reinterpret_cast<unsigned long long*>(L.barrier + 2);
   B.spin_limit = L.spin_limit;
-#define NLSE_LB(TX_, TY_)                                                                                   \
-  if (L.tx == TX_ && L.ty == TY_) {                                                                         \
-    hipLaunchKernelGGL((batch2d_kernel<T, COMP, TX_, TY_>), dim3(L.nchunks), dim3(TX_ * TY_), 0, st, B, L.nsteps, \
-                       L.stages);                                                                           \
-    return hipGetLastError();                                                                               \
+#define NLSE_LB(TX_, TY_)                                                                                          \
+  if (L.tx == TX_ && L.ty == TY_) {                                                                                \
+    if (L.pairs)                                                                                                   \
+      hipLaunchKernelGGL((batch2d_pair_kernel<T, COMP, TX_, TY_>), dim3(L.nchunks), dim3(TX_ * TY_), 0, st, B,     \
+                         L.nsteps);                                                                                \
+    else                                                                                                           \
+      hipLaunchKernelGGL((batch2d_kernel<T, COMP, TX_, TY_>), dim3(L.nchunks), dim3(TX_ * TY_), 0, st, B, L.nsteps); \
+    return hipGetLastError();                                                                                      \
   }
   NLSE_LB(32, 8)
   NLSE_LB(64, 4)
@@ -303,10 +425,11 @@ hipError_t nlse_launch_batch(const nlse::BatchLaunch& L, hipStream_t st) {
   return nlse::launch_typed<double, 0>(L, st);
 }
 
-// Workgroups of the batched kernel with tile tx x ty that one CU holds at once.
-hipError_t nlse_batch_occupancy(int dtype, int comp, int tx, int ty, int* blocks_per_cu) {
-  const void* k = dtype == 0 ? (comp ? nlse::kernel_ptr<float, 1>(tx, ty) : nlse::kernel_ptr<float, 0>(tx, ty))
-                             : nlse::kernel_ptr<double, 0>(tx, ty);
+// Workgroups of the batched kernel with tile tx x ty (stage pairs or not)
+// that one CU holds at once.
+hipError_t nlse_batch_occupancy(int dtype, int comp, int tx, int ty, int pairs, int* blocks_per_cu) {
+  const void* k = dtype == 0 ? (comp ? nlse::kernel_ptr<float, 1>(tx, ty, pairs) : nlse::kernel_ptr<float, 0>(tx, ty, pairs))
+                             : nlse::kernel_ptr<double, 0>(tx, ty, pairs);
   if (!k) return hipErrorInvalidValue;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, tx * ty, 0);
 }

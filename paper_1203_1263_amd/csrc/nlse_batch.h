@@ -32,7 +32,8 @@ static_assert(sizeof(BatchItem) == 128, "BatchItem is read as 32 dwords");
 struct BatchLaunch {
   int dtype, comp, nsteps, nchunks;
   int tx, ty;  // tile (one of kBatchTiles)
-  int stages;  // RK4 stages run per step: 4, or 3 for timing (Psi is not written)
+  int pairs;   // 1: two stage-pair passes per step (Psi alternates with bufA
+               // inside a launch; nsteps must be even), 0: four single-stage passes
   const BatchItem* items;
   const int* chunk_off;  // nchunks + 1 item offsets, then per chunk its group
                          // (-1: the chunk owns whole problems), then the group size
@@ -47,4 +48,4 @@ struct BatchLaunch {
 }  // namespace nlse
 
 hipError_t nlse_launch_batch(const nlse::BatchLaunch& L, hipStream_t st);
-hipError_t nlse_batch_occupancy(int dtype, int comp, int tx, int ty, int* blocks_per_cu);
+hipError_t nlse_batch_occupancy(int dtype, int comp, int tx, int ty, int pairs, int* blocks_per_cu);

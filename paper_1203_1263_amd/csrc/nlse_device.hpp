@@ -178,29 +178,46 @@ __device__ __forceinline__ void load_own(const StageArgs<T>& A, int64_t i, Own<T
   }
 }
 
-template <typename T, int STAGE, int COMP, bool STREAM = false>
-__device__ __forceinline__ void stage_update(const StageArgs<T>& A, int64_t i, cpx<T> u, cpx<T> K,
-                                             const Own<T>& o) {
-  const T ca = A.c_acc, cn = A.c_next;
+// The values a stage writes for one point: the accumulator (stages 1-3),
+// the next stage input or, at stage 4, Psi, and (stage 4, compensated) the
+// new compensation term.  u is the point's stage input (Psi itself at stage
+// 1); o its own operands.
+template <typename T>
+struct StageOut {
+  cpx<T> acc, out, lo;
+};
+
+template <typename T, int STAGE, int COMP>
+__device__ __forceinline__ StageOut<T> stage_values(T ca, T cn, double ca_d, cpx<T> u, cpx<T> K, const Own<T>& o) {
+  StageOut<T> r;
   if constexpr (STAGE == 1) {
-    cpx<T> acc = COMP ? mk<T>(ca * K.re, ca * K.im) : mk<T>(fmaT(ca, K.re, u.re), fmaT(ca, K.im, u.im));
-    st_own<T, STREAM>(A.acc + i, acc);
-    st_own<T, STREAM>(A.uout + i, mk<T>(fmaT(cn, K.re, u.re), fmaT(cn, K.im, u.im)));
+    r.acc = COMP ? mk<T>(ca * K.re, ca * K.im) : mk<T>(fmaT(ca, K.re, u.re), fmaT(ca, K.im, u.im));
+    r.out = mk<T>(fmaT(cn, K.re, u.re), fmaT(cn, K.im, u.im));
   } else if constexpr (STAGE == 2 || STAGE == 3) {
-    st_own<T, STREAM>(A.acc + i, mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im)));
-    st_own<T, STREAM>(A.uout + i, mk<T>(fmaT(cn, K.re, o.psi.re), fmaT(cn, K.im, o.psi.im)));
+    r.acc = mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im));
+    r.out = mk<T>(fmaT(cn, K.re, o.psi.re), fmaT(cn, K.im, o.psi.im));
   } else if constexpr (!COMP) {
-    st_own<T, STREAM>(A.uout + i, mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im)));
+    r.out = mk<T>(fmaT(ca, K.re, o.acc.re), fmaT(ca, K.im, o.acc.im));
   } else {
     // Psi_hi + Psi_lo + (acc + k/6 K4), summed in FP64 and split back.
-    double inc_r = __builtin_fma(A.c_acc_d, (double)K.re, (double)o.acc.re);
-    double inc_i = __builtin_fma(A.c_acc_d, (double)K.im, (double)o.acc.im);
+    double inc_r = __builtin_fma(ca_d, (double)K.re, (double)o.acc.re);
+    double inc_i = __builtin_fma(ca_d, (double)K.im, (double)o.acc.im);
     double sr = ((double)o.psi.re + (double)o.lo.re) + inc_r;
     double si = ((double)o.psi.im + (double)o.lo.im) + inc_i;
     T hr = (T)sr, hi = (T)si;
-    st_own<T, STREAM>(A.uout + i, mk<T>(hr, hi));
-    st_own<T, STREAM>(A.lo + i, mk<T>((T)(sr - (double)hr), (T)(si - (double)hi)));
+    r.out = mk<T>(hr, hi);
+    r.lo = mk<T>((T)(sr - (double)hr), (T)(si - (double)hi));
   }
+  return r;
+}
+
+template <typename T, int STAGE, int COMP, bool STREAM = false>
+__device__ __forceinline__ void stage_update(const StageArgs<T>& A, int64_t i, cpx<T> u, cpx<T> K,
+                                             const Own<T>& o) {
+  const StageOut<T> r = stage_values<T, STAGE, COMP>(A.c_acc, A.c_next, A.c_acc_d, u, K, o);
+  if constexpr (STAGE <= 3) st_own<T, STREAM>(A.acc + i, r.acc);
+  st_own<T, STREAM>(A.uout + i, r.out);
+  if constexpr (STAGE == 4 && COMP) st_own<T, STREAM>(A.lo + i, r.lo);
 }
 
 // ---------------------------------------------------------------- tiles

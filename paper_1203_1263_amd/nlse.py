@@ -94,7 +94,7 @@ def load_library() -> ctypes.CDLL:
         "nlse_batch_mass_energy": (ctypes.c_int, [vp, dp, dp]),
         "nlse_batch_status": (ctypes.c_int, [vp]),
         "nlse_batch_info": (ctypes.c_int, [vp, i64p]),
-        "nlse_batch_set_config": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+        "nlse_batch_set_config": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
         "nlse_batch_get_config": (ctypes.c_int, [vp, ip]),
         "nlse_batch_autotune": (ctypes.c_int, [vp]),
         "nlse_batch_destroy": (ctypes.c_int, [vp]),
@@ -255,14 +255,14 @@ def nlse_batch_info(b):
     return {"workgroups": info[0], "items": info[1], "points": info[2], "graphs": info[3]}
 
 
-def nlse_batch_set_config(b, tx: int, ty: int, wg_per_cu: int):
-    _check(load_library().nlse_batch_set_config(b, tx, ty, wg_per_cu), "nlse_batch_set_config")
+def nlse_batch_set_config(b, tx: int, ty: int, wg_per_cu: int, pairs: int = 0):
+    _check(load_library().nlse_batch_set_config(b, tx, ty, wg_per_cu, int(pairs)), "nlse_batch_set_config")
 
 
-def nlse_batch_get_config(b) -> Tuple[int, int, int]:
-    c = (ctypes.c_int * 3)()
+def nlse_batch_get_config(b) -> Tuple[int, int, int, int]:
+    c = (ctypes.c_int * 4)()
     _check(load_library().nlse_batch_get_config(b, c), "nlse_batch_get_config")
-    return c[0], c[1], c[2]
+    return c[0], c[1], c[2], c[3]
 
 
 def nlse_batch_autotune(b):
@@ -526,11 +526,12 @@ class Batch:
     def info(self):
         return nlse_batch_info(self._b)
 
-    def set_config(self, tx: int, ty: int, wg_per_cu: int):
-        nlse_batch_set_config(self._b, tx, ty, wg_per_cu)
+    def set_config(self, tx: int, ty: int, wg_per_cu: int, pairs: bool = False):
+        nlse_batch_set_config(self._b, tx, ty, wg_per_cu, 1 if pairs else 0)
 
     def config(self):
-        """(tile x-width, tile y-height, persistent workgroups per CU)."""
+        """(tile x-width, tile y-height, persistent workgroups per CU,
+        1 if a step runs as two stage-pair passes else 0)."""
         return nlse_batch_get_config(self._b)
 
     def autotune(self):

@@ -90,7 +90,7 @@ static void validation() {
   d[0].dims[0] = 2;
   EXPECT(nlse_batch_workspace_bytes(2, d.data(), NLSE_F32, 0, &bytes) == NLSE_EINVAL);
   EXPECT(nlse_batch_step_rk4(nullptr, -1) == NLSE_EINVAL);
-  EXPECT(nlse_batch_set_config(nullptr, 32, 8, 3) == NLSE_EINVAL);
+  EXPECT(nlse_batch_set_config(nullptr, 32, 8, 3, 0) == NLSE_EINVAL);
 }
 
 static void planner() {

@@ -78,21 +78,27 @@ def test_batch_matches_oracle_and_single_grid(dtype, comp, graph):
     b.close()
 
 
-@pytest.mark.parametrize("tile,wg", [((64, 4), 2), ((64, 8), 4), ((32, 8), 5), ((64, 4), 16), ((128, 4), 2),
-                                     ((64, 16), 1)],
-                         ids=["64x4-w2", "64x8-w4", "32x8-w5", "64x4-w16", "128x4-w2", "64x16-w1"])
-def test_every_tile_and_grid_size_equals_single_grid(tile, wg):
+@pytest.mark.parametrize("tile,wg,pairs", [((64, 4), 2, False), ((64, 8), 4, False), ((32, 8), 5, False),
+                                           ((64, 4), 16, False), ((128, 4), 2, False), ((64, 16), 1, False),
+                                           ((32, 8), 3, True), ((64, 4), 2, True), ((64, 8), 2, True),
+                                           ((128, 4), 2, True), ((64, 16), 1, True), ((64, 16), 2, True)],
+                         ids=["64x4-w2", "64x8-w4", "32x8-w5", "64x4-w16", "128x4-w2", "64x16-w1",
+                              "pairs-32x8-w3", "pairs-64x4-w2", "pairs-64x8-w2", "pairs-128x4-w2", "pairs-64x16-w1",
+                              "pairs-64x16-w2"])
+def test_every_tile_and_grid_size_equals_single_grid(tile, wg, pairs):
     """Every configuration the autotuner may choose: the batch with tile
-    (tx, ty) and wg workgroups per CU is bitwise equal to single grids run
-    with the same tile, and within 1e-5 of the oracle (compensated FP32),
-    after a reconfiguration from the default and with graph replays."""
+    (tx, ty), wg workgroups per CU and four single-stage or two stage-pair
+    passes per step is bitwise equal to single grids run with the same tile,
+    and within 1e-5 of the oracle (compensated FP32), after a
+    reconfiguration from the default and with graph replays of an even and
+    an odd step count (an odd count starts with a three-pass step)."""
     import torch
     from paper_1203_1263_amd.nlse import Batch, Grid
     from gpu_util import to_dev, pot_dev
     probs, dts = small_batch(11)
     b2 = Batch(probs, dts, compensated=True)  # created with the default configuration
-    b2.set_config(tile[0], tile[1], wg)
-    assert b2.config() == (tile[0], tile[1], wg)
+    b2.set_config(tile[0], tile[1], wg, pairs)
+    assert b2.config() == (tile[0], tile[1], wg, int(pairs))
     n = 9
     b2.step(4)
     b2.step(5)
@@ -129,6 +135,7 @@ def test_autotune_keeps_fields_and_caches_its_choice(tmp_path, monkeypatch):
     assert torch.equal(before, b.pool)
     cfg = b.config()
     assert (cfg[0], cfg[1]) in ((32, 8), (64, 4), (64, 8), (128, 4), (64, 16)) and 1 <= cfg[2] <= 5
+    assert cfg[3] in (0, 1)
     b.step(4)
     b.status()
     ref = Batch(probs, dts, compensated=True)
@@ -143,6 +150,35 @@ def test_autotune_keeps_fields_and_caches_its_choice(tmp_path, monkeypatch):
     assert b3.config() == cfg
     for x in (b, ref, b3):
         x.close()
+
+
+@pytest.mark.parametrize("dtype,comp", [("f32", False), ("f64", False), ("f32", True)])
+def test_stage_pairs_equal_four_passes_in_every_mode(dtype, comp):
+    """Two stage-pair passes per step give the bits of four single-stage
+    passes (same tile), in every element type and mode, for calls of 1, 2
+    and 3 steps (Psi alternates with a work buffer inside a call and must be
+    back in the caller's pool after each), directly and through graphs."""
+    import torch
+    from paper_1203_1263_amd.nlse import Batch
+    probs, dts = small_batch(17)
+    for graph in (False, True):
+        four = Batch(probs, dts, dtype=dtype, compensated=comp, graph=graph)
+        two = Batch(probs, dts, dtype=dtype, compensated=comp, graph=graph)
+        four.set_config(64, 8, 2, False)
+        two.set_config(64, 8, 2, True)
+        for n in (1, 2, 3):
+            four.step(n)
+            two.step(n)
+            torch.cuda.synchronize()
+            assert torch.equal(four.pool, two.pool), f"after a call of {n} steps (graph={graph})"
+        four.status()
+        two.status()
+        if dtype == "f64":
+            for j, (p, dt) in enumerate(zip(probs, dts)):
+                ref = oracle.rk4(p.psi0, p.h, p.a, p.s, dt, 6, V=p.V, order=p.order, bc=p.bc)
+                assert rel_l2(two.field(j).cpu().numpy(), ref) < 1e-11, f"problem {j}"
+        four.close()
+        two.close()
 
 
 def test_graph_replays_match_direct_launches():
