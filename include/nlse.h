@@ -274,7 +274,7 @@ int nlse_batch_mass_energy(nlse_batch *b, double *mass, double *energy);
  * out since creation (the fields are then not valid), else NLSE_OK. */
 int nlse_batch_status(nlse_batch *b);
 
-/* Tile (tx x ty: 32x8, 64x4, 64x8, 128x4 or 64x16), persistent workgroups
+/* Tile (tx x ty: 32x8, 64x4, 64x8, 128x4, 64x16, 32x16 or 32x32), persistent workgroups
  * per CU (1..16; the grid holds min(wg_per_cu, what fits on a CU) x CUs
  * workgroups) and pass structure of the batched kernel: pairs = 0 runs the
  * four RK4 stages as four passes over the batch, pairs = 1 as two passes of

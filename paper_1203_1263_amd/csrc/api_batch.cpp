@@ -196,8 +196,7 @@ static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, int TX, in
     std::memset(&s, 0, sizeof s);
     s.nx = (int)d.dims[0];
     s.ny = (int)d.dims[1];
-    s.order = d.order;
-    s.bc = d.bc;
+    s.scheme = d.order | (d.bc << 8);
     s.psi_off = d.psi_offset;
     s.v_off = d.v_offset;
     s.woff = woff;
@@ -211,6 +210,15 @@ static int plan_schedule(int nsims, const nlse_sim_desc* sims, int W, int TX, in
     s.dt2 = d.dt / 2.0;
     s.dt3 = d.dt / 3.0;
     s.dt6 = d.dt / 6.0;
+    s.af = (float)s.a;
+    s.sf = (float)s.s;
+    s.inv_af = (float)s.inv_a;
+    s.inv_h2f = (float)s.inv_h2;
+    s.inv_6h2f = (float)s.inv_6h2;
+    s.dtf = (float)s.dt;
+    s.dt2f = (float)s.dt2;
+    s.dt3f = (float)s.dt3;
+    s.dt6f = (float)s.dt6;
     s.sim = j;
     const int ntx = (s.nx + TX - 1) / TX, nty = (s.ny + TY - 1) / TY;
     const double c = (d.order == 4 ? 1.35 : 1.0) * (d.v_offset >= 0 ? 1.1 : 1.0);

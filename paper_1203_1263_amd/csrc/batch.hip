@@ -92,8 +92,8 @@ __device__ __forceinline__ bool group_barrier(unsigned* flag, unsigned long long
   return ok != 0;
 }
 
-// Dword k of the descriptor words held one per lane (lanes l and l + 32
-// hold dword l), broadcast to the whole wave.
+// Dword k of the descriptor words held one per lane, broadcast to the
+// whole wave.
 __device__ __forceinline__ int word_i32(unsigned w, int k) { return __builtin_amdgcn_readlane((int)w, k); }
 __device__ __forceinline__ int64_t word_i64(unsigned w, int k) {
   return (int64_t)(((uint64_t)(unsigned)word_i32(w, k + 1) << 32) | (uint64_t)(unsigned)word_i32(w, k));
@@ -101,11 +101,21 @@ __device__ __forceinline__ int64_t word_i64(unsigned w, int k) {
 __device__ __forceinline__ double word_f64(unsigned w, int k) {
   return __builtin_bit_cast(double, (uint64_t)word_i64(w, k));
 }
+// A physical constant in the element type: the FP32 copy (one dword) for
+// FP32 kernels, the double for FP64 ones.
+template <typename T>
+__device__ __forceinline__ T word_t(unsigned w, int kd, int kf) {
+  if constexpr (sizeof(T) == 4)
+    return __builtin_bit_cast(float, word_i32(w, kf));
+  else
+    return word_f64(w, kd);
+}
 #define NLSE_WORD(field) ((int)(offsetof(BatchItem, field) / 4))
+#define NLSE_WORD_T(field) word_t<T>(w, NLSE_WORD(field), NLSE_WORD(field##f))
 
 // The descriptor of item `it`, one dword per lane.
 __device__ __forceinline__ unsigned item_words(const BatchItem* items, int it) {
-  return reinterpret_cast<const unsigned*>(items + it)[threadIdx.x & 31];
+  return reinterpret_cast<const unsigned*>(items + it)[threadIdx.x & 63];
 }
 
 template <typename T>
@@ -134,18 +144,17 @@ __device__ __forceinline__ ItemArgs<T> decode(const BatchArgs<T>& B, unsigned w)
   A.nx = word_i32(w, NLSE_WORD(nx));
   A.ny = word_i32(w, NLSE_WORD(ny));
   A.nz = 1;
-  A.ph.a = (T)word_f64(w, NLSE_WORD(a));
-  A.ph.s = (T)word_f64(w, NLSE_WORD(s));
-  A.ph.inv_a = (T)word_f64(w, NLSE_WORD(inv_a));
-  A.ph.inv_h2 = (T)word_f64(w, NLSE_WORD(inv_h2));
-  A.ph.inv_6h2 = (T)word_f64(w, NLSE_WORD(inv_6h2));
-  const double ca = (STAGE == 1 || STAGE == 4) ? word_f64(w, NLSE_WORD(dt6)) : word_f64(w, NLSE_WORD(dt3));
-  const double cn = STAGE == 3 ? word_f64(w, NLSE_WORD(dt)) : word_f64(w, NLSE_WORD(dt2));
-  A.c_acc = (T)ca;
-  A.c_next = (T)cn;
-  A.c_acc_d = ca;
-  I.order = word_i32(w, NLSE_WORD(order));
-  I.bc = word_i32(w, NLSE_WORD(bc));
+  A.ph.a = NLSE_WORD_T(a);
+  A.ph.s = NLSE_WORD_T(s);
+  A.ph.inv_a = NLSE_WORD_T(inv_a);
+  A.ph.inv_h2 = NLSE_WORD_T(inv_h2);
+  A.ph.inv_6h2 = NLSE_WORD_T(inv_6h2);
+  A.c_acc = (STAGE == 1 || STAGE == 4) ? NLSE_WORD_T(dt6) : NLSE_WORD_T(dt3);
+  A.c_next = STAGE == 3 ? NLSE_WORD_T(dt) : NLSE_WORD_T(dt2);
+  A.c_acc_d = (STAGE == 1 || STAGE == 4) ? word_f64(w, NLSE_WORD(dt6)) : word_f64(w, NLSE_WORD(dt3));
+  const int scheme = word_i32(w, NLSE_WORD(scheme));
+  I.order = scheme & 0xff;
+  I.bc = scheme >> 8;
   I.tx = word_i32(w, NLSE_WORD(tx));
   I.ty = word_i32(w, NLSE_WORD(ty));
   return I;
@@ -177,26 +186,26 @@ __device__ __forceinline__ PairItem<T> decode_pair(const BatchArgs<T>& B, unsign
   A.vs = v_off >= 0 ? 1 : 0;
   A.nx = word_i32(w, NLSE_WORD(nx));
   A.ny = word_i32(w, NLSE_WORD(ny));
-  A.ph.a = (T)word_f64(w, NLSE_WORD(a));
-  A.ph.s = (T)word_f64(w, NLSE_WORD(s));
-  A.ph.inv_a = (T)word_f64(w, NLSE_WORD(inv_a));
-  A.ph.inv_h2 = (T)word_f64(w, NLSE_WORD(inv_h2));
-  A.ph.inv_6h2 = (T)word_f64(w, NLSE_WORD(inv_6h2));
-  const double dt = word_f64(w, NLSE_WORD(dt)), dt2 = word_f64(w, NLSE_WORD(dt2));
-  const double dt3 = word_f64(w, NLSE_WORD(dt3)), dt6 = word_f64(w, NLSE_WORD(dt6));
+  A.ph.a = NLSE_WORD_T(a);
+  A.ph.s = NLSE_WORD_T(s);
+  A.ph.inv_a = NLSE_WORD_T(inv_a);
+  A.ph.inv_h2 = NLSE_WORD_T(inv_h2);
+  A.ph.inv_6h2 = NLSE_WORD_T(inv_6h2);
   // the coefficients of stages 1, 2 (PAIR 1) or 3, 4 (PAIR 2) as decode gives them
-  A.ca1 = (T)(PAIR == 1 ? dt6 : dt3);
-  A.cn1 = (T)(PAIR == 1 ? dt2 : dt);
-  A.ca2 = (T)(PAIR == 1 ? dt3 : dt6);
-  A.cn2 = (T)dt2;  // stage 2; stage 4 has none
-  A.ca2_d = PAIR == 1 ? dt3 : dt6;
-  I.order = word_i32(w, NLSE_WORD(order));
-  I.bc = word_i32(w, NLSE_WORD(bc));
+  A.ca1 = PAIR == 1 ? NLSE_WORD_T(dt6) : NLSE_WORD_T(dt3);
+  A.cn1 = PAIR == 1 ? NLSE_WORD_T(dt2) : NLSE_WORD_T(dt);
+  A.ca2 = PAIR == 1 ? NLSE_WORD_T(dt3) : NLSE_WORD_T(dt6);
+  A.cn2 = NLSE_WORD_T(dt2);  // stage 2; stage 4 has none
+  A.ca2_d = PAIR == 1 ? word_f64(w, NLSE_WORD(dt3)) : word_f64(w, NLSE_WORD(dt6));
+  const int scheme = word_i32(w, NLSE_WORD(scheme));
+  I.order = scheme & 0xff;
+  I.bc = scheme >> 8;
   I.tx = word_i32(w, NLSE_WORD(tx));
   I.ty = word_i32(w, NLSE_WORD(ty));
   return I;
 }
 #undef NLSE_WORD
+#undef NLSE_WORD_T
 
 // The items [i0, i1) of a chunk, software-pipelined.  Item `it`: its loads
 // are in flight in `cur`, its descriptor words (long arrived) are in `wc`,
@@ -380,6 +389,8 @@ static const void* kernel_ptr(int tx, int ty, int pairs) {
   NLSE_KP(64, 8)
   NLSE_KP(128, 4)
   NLSE_KP(64, 16)
+  NLSE_KP(32, 16)
+  NLSE_KP(32, 32)
 #undef NLSE_KP
   return nullptr;
 }
@@ -414,6 +425,8 @@ static hipError_t launch_typed(const BatchLaunch& L, hipStream_t st) {
   NLSE_LB(64, 8)
   NLSE_LB(128, 4)
   NLSE_LB(64, 16)
+  NLSE_LB(32, 16)
+  NLSE_LB(32, 32)
 #undef NLSE_LB
   return hipErrorInvalidValue;
 }

@@ -23,7 +23,10 @@ extern "C" int nlse_internal_tile_supported(int ndim, int dtype, const int tile[
   // 1D: 256 = per-stage kernels, 1024 = whole-grid kernel (small grids)
   if (ndim == 1) return (tx == 256 || tx == 1024) && ty == 1 && cz == 1;
   const bool xy = (tx == 32 && ty == 8) || (tx == 64 && ty == 4) || (tx == 64 && ty == 8);
-  // 2D also: 128x4 and 64x16 (the batched integrator's larger tiles)
-  if (ndim == 2) return (xy || (tx == 128 && ty == 4) || (tx == 64 && ty == 16)) && cz == 1;
+  // 2D also: 128x4, 64x16, 32x16 and 32x32 (the batched integrator's other tiles)
+  if (ndim == 2)
+    return (xy || (tx == 128 && ty == 4) || (tx == 64 && ty == 16) || (tx == 32 && ty == 16) ||
+            (tx == 32 && ty == 32)) &&
+           cz == 1;
   return xy && cz >= 1 && cz <= 4096;
 }

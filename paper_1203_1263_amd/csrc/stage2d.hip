@@ -31,6 +31,8 @@ struct Launch2D {
     NLSE_L2(64, 8)
     NLSE_L2(128, 4)
     NLSE_L2(64, 16)
+    NLSE_L2(32, 16)
+    NLSE_L2(32, 32)
 #undef NLSE_L2
     return hipErrorInvalidValue;
   }

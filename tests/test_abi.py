@@ -162,8 +162,8 @@ def _plan(descs, W, tile=(32, 8)):
     return c[:W + 1], [tuple(c[W + 1 + 4 * k:W + 5 + 4 * k]) for k in range(W)], list(items), ng.value, nitems
 
 
-@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (64, 8), (128, 4), (64, 16)],
-                         ids=["32x8", "64x4", "64x8", "128x4", "64x16"])
+@pytest.mark.parametrize("tile", [(32, 8), (64, 4), (64, 8), (128, 4), (64, 16), (32, 16), (32, 32)],
+                         ids=["32x8", "64x4", "64x8", "128x4", "64x16", "32x16", "32x32"])
 @pytest.mark.parametrize("seed,nsims,W", [(0, 40, 64), (1, 512, 768), (2, 7, 200), (3, 3, 1), (4, 30, 4096)])
 def test_batch_schedule_invariants(seed, nsims, W, tile):
     """The batched integrator's static schedule (host logic), for every tile

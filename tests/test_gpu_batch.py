@@ -81,10 +81,12 @@ def test_batch_matches_oracle_and_single_grid(dtype, comp, graph):
 @pytest.mark.parametrize("tile,wg,pairs", [((64, 4), 2, False), ((64, 8), 4, False), ((32, 8), 5, False),
                                            ((64, 4), 16, False), ((128, 4), 2, False), ((64, 16), 1, False),
                                            ((32, 8), 3, True), ((64, 4), 2, True), ((64, 8), 2, True),
-                                           ((128, 4), 2, True), ((64, 16), 1, True), ((64, 16), 2, True)],
+                                           ((128, 4), 2, True), ((64, 16), 1, True), ((64, 16), 2, True),
+                                           ((32, 16), 2, False), ((32, 32), 1, False), ((32, 16), 2, True),
+                                           ((32, 32), 1, True)],
                          ids=["64x4-w2", "64x8-w4", "32x8-w5", "64x4-w16", "128x4-w2", "64x16-w1",
                               "pairs-32x8-w3", "pairs-64x4-w2", "pairs-64x8-w2", "pairs-128x4-w2", "pairs-64x16-w1",
-                              "pairs-64x16-w2"])
+                              "pairs-64x16-w2", "32x16-w2", "32x32-w1", "pairs-32x16-w2", "pairs-32x32-w1"])
 def test_every_tile_and_grid_size_equals_single_grid(tile, wg, pairs):
     """Every configuration the autotuner may choose: the batch with tile
     (tx, ty), wg workgroups per CU and four single-stage or two stage-pair
@@ -134,7 +136,8 @@ def test_autotune_keeps_fields_and_caches_its_choice(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(before, b.pool)
     cfg = b.config()
-    assert (cfg[0], cfg[1]) in ((32, 8), (64, 4), (64, 8), (128, 4), (64, 16)) and 1 <= cfg[2] <= 5
+    assert (cfg[0], cfg[1]) in ((32, 8), (64, 4), (64, 8), (128, 4), (64, 16), (32, 16), (32, 32))
+    assert 1 <= cfg[2] <= 5
     assert cfg[3] in (0, 1)
     b.step(4)
     b.status()

@@ -81,7 +81,7 @@ def test_no_potential_matches_zero_potential(nd):
 
 def _tiles(nd):
     if nd == 2:
-        return [(64, 4, 1), (64, 8, 1), (32, 8, 1), (128, 4, 1), (64, 16, 1)]
+        return [(64, 4, 1), (64, 8, 1), (32, 8, 1), (128, 4, 1), (64, 16, 1), (32, 16, 1), (32, 32, 1)]
     return [(64, 4, 8), (64, 8, 5), (32, 8, 3), (32, 8, 16), (64, 4, 1)]
 
 
