@@ -33,8 +33,18 @@
 
 namespace nlse {
 
+// The compensated MSD stage 4 on the 32x8 tile holds the most registers
+// (102, four waves per SIMD); asking for five waves costs it one
+// loop-invariant 8-byte reload per plane and is slightly faster (Dirichlet
+// and L0 would spill 11-12 registers, so they keep four).
+template <int STAGE, int COMP, int BC, int TX, int TY>
+constexpr int stage3d_min_waves() {
+  return (STAGE == 4 && COMP && BC == kMSD && TX == 32 && TY == 8) ? 5 : 1;
+}
+
 template <typename T, int ORDER, int BC, int STAGE, int COMP, int TX, int TY, bool STREAM>
-__global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz) {
+__global__ __launch_bounds__(TX* TY) __attribute__((amdgpu_waves_per_eu(stage3d_min_waves<STAGE, COMP, BC, TX, TY>())))
+void stage3d_kernel(StageArgs<T> A, int cz) {
   constexpr int NT = TX * TY;
   constexpr int H = ORDER == 4 ? 2 : 1;
   constexpr int BW = TX + 2 * H, BH = TY + 2 * H, BSZ = BW * BH;
@@ -53,7 +63,9 @@ __global__ __launch_bounds__(TX* TY) void stage3d_kernel(StageArgs<T> A, int cz)
   };
 
   const int nx = A.nx, ny = A.ny, nz = A.nz;
-  const int64_t ps = (int64_t)nx * ny;
+  // points per plane: below 2^31 (checked on the host), so every plane
+  // offset is a widening 32 x 32-bit product on the scalar unit
+  const int ps = nx * ny;
   const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
   const int t = xcd_swizzle(blockIdx.x, gridDim.x);
   const int tx = t % ntx, ty = (t / ntx) % nty, zc = t / (ntx * nty);
