@@ -42,7 +42,10 @@ BYTES_PER_PT_STEP = {"compensated": 168, "plain": 144}
 # the compensated 256^3 run with tile (32, 8, 16); reported only for that
 # configuration.
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA
-MEASURED_TRAFFIC = {("compensated", 256, (32, 8, 16)): 751.1e6}
+MEASURED_TRAFFIC = {("compensated", 256, (32, 8, 16)): 756.3e6}
+# HBM bytes per point-step of the batched workload's kernel, from FETCH_SIZE /
+# WRITE_SIZE counters, keyed by (tile, stage pairs, mode)
+BATCH_TRAFFIC = {((32, 32), True, "compensated"): 84.4}
 
 
 def parse():
@@ -130,6 +133,8 @@ def run_batch(args, steps):
     # 28 + 36 B plain); the roofline stays against the four-pass figure
     kbpp = (80 if not args.plain else 64) if pairs else bpp
     achieved = npts * bpp * steps / gpu_s / 1e9
+    tb = BATCH_TRAFFIC.get(((tx, ty), bool(pairs), "plain" if args.plain else "compensated"))
+    traffic = tb * npts * steps if tb else None  # HBM bytes of the timed launch
     out = {"metric": "grid-point RK4 updates/s (512 batched 2D problems)", "value": npts * steps / wall,
            "unit": "grid-point RK4 updates/s", "n_gpus": 1, "steps": steps, "warmup": steps,
            "ms_per_step": wall * 1e3 / steps, "higher_is_better": True, "scaling": "weak",
@@ -140,7 +145,7 @@ def run_batch(args, steps):
                       "tile": [tx, ty], "wg_per_cu": wg, "stage_pairs": bool(pairs), "autotuned": True,
                       "autotune_s": t_tune},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                         "kernel": "batch2d_pair_kernel (persistent, stage pairs)" if pairs
                         else "batch2d_kernel (persistent, all stages)",
                         "bytes_per_point_step": bpp, "kernel_bytes_per_point_step": kbpp,
@@ -345,7 +350,7 @@ def batch_summary(args):
     keep = ("value", "unit", "ms_per_step", "steps")
     out = {k: r[k] for k in keep}
     out["config"] = {k: r["config"][k] for k in ("points", "tile", "wg_per_cu", "stage_pairs", "autotune_s")}
-    out["roofline"] = {k: r["roofline"][k] for k in ("achieved", "frac", "bytes_per_point_step",
+    out["roofline"] = {k: r["roofline"][k] for k in ("achieved", "frac", "traffic", "bytes_per_point_step",
                                                      "kernel_bytes_per_point_step", "kernel_GBps", "kernel")}
     return out
 
