@@ -73,13 +73,17 @@ enum { NLSE_BC_DIRICHLET = 0, NLSE_BC_MSD = 1, NLSE_BC_L0 = 2 };
                                  combination of the last stage done in FP64 */
 #define NLSE_NO_GRAPH 0x2u    /* grid or batch: launch directly instead of
                                  replaying captured HIP graphs */
-#define NLSE_FUSED_PAIRS 0x4u /* grid only, 3D FP32 2SHOC on the 32x8 tile:
-                                 run each pair of RK4 steps as four fused
-                                 launches (stages 1+2, 3+4 per step) that
-                                 keep U1 and U3 on chip (80 instead of 168 B
-                                 per point-step, same bits).  Off by
-                                 default: at 2 workgroups per CU it is
-                                 currently slower than four passes. */
+#define NLSE_FUSED_PAIRS 0x4u /* grid only: run each pair of RK4 steps as
+                                 four stage-pair launches (stages 1+2, 3+4
+                                 per step) that keep U1 and U3 on chip (80
+                                 instead of 168 B per point-step compensated,
+                                 same bits); an odd last step takes four
+                                 passes.  2D grids: every type, scheme and
+                                 boundary condition, on the 64x16 tile if it
+                                 is the grid's, else 32x32.  3D grids: FP32
+                                 2SHOC, Dirichlet / MSD, on the 32x8 tile
+                                 (slower than four passes there: 2
+                                 workgroups per CU).  Off by default. */
 
 typedef struct nlse_grid nlse_grid;
 
@@ -205,7 +209,8 @@ int nlse_set_state(nlse_grid *g, const void *lo_dev);
  * step of a call in one on-chip workgroup.  nlse_autotune times the candidates for
  * (order, bc) on this grid (running stage kernels on scratch copies, the
  * field is not changed; for fused 3D grids only the z-chunk of the 32x8
- * tile is tuned), keeps the fastest and stores it in the cache file
+ * tile is tuned, for 2D grids with NLSE_FUSED_PAIRS the pair tile, 32x32
+ * or 64x16), keeps the fastest and stores it in the cache file
  * named by $NLSE_TUNE_CACHE if set.  nlse_set_tile forces a shape
  * (NLSE_EUNSUPPORTED if it is not a compiled candidate). */
 int nlse_autotune(nlse_grid *g, int order, int bc, double dt);

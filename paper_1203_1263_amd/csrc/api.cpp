@@ -195,6 +195,10 @@ extern "C" int nlse_workspace_bytes(int ndim, const int64_t dims[3], int dtype, 
 static bool fused_eligible(const Shape& s, int dtype, unsigned flags, int order) {
   return s.ndim == 3 && dtype == NLSE_F32 && order == 4 && (flags & NLSE_FUSED_PAIRS);
 }
+// A 2D grid created with NLSE_FUSED_PAIRS runs each step as two stage-pair
+// launches (every type, scheme and boundary condition) on the 64x16 tile if
+// that is its tile, else on 32x32.
+static bool pairs2d_eligible(const Shape& s, unsigned flags) { return s.ndim == 2 && (flags & NLSE_FUSED_PAIRS); }
 
 static void default_tile(const Shape& s, int dtype, unsigned flags, int order, int t[3]) {
   if (s.ndim == 1) {
@@ -357,7 +361,27 @@ static hipError_t enqueue_steps(const nlse_grid* g, int order, int bc, double dt
     return nlse_launch_resident1d(L, nsteps, dt, st);
   }
   int64_t left = nsteps;
-  if (bc != NLSE_BC_L0 && fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 && tile[1] == 8) {
+  if (pairs2d_eligible(g->shape, g->flags)) {
+    // Pairs of steps Psi -> workspace -> Psi, as below; the first pass of
+    // each step writes U2 to bufA
+    nlse::StageLaunch L = grid_launch(g, order, bc, tile);
+    if (!(tile[0] == 64 && tile[1] == 16)) {
+      L.tile[0] = 32;
+      L.tile[1] = 32;
+    }
+    void* acc = g->work + g->lay.acc;
+    void* u2 = g->work + g->lay.bufA;
+    void* alt = g->work + g->lay.bufB;
+    void* lo = L.comp ? g->work + g->lay.lo : nullptr;
+    for (; left >= 2; left -= 2) {
+      hipError_t e = nlse_launch_pair2d(L, g->psi, alt, acc, u2, lo, dt, 1, st);
+      if (e == hipSuccess) e = nlse_launch_pair2d(L, g->psi, alt, acc, u2, lo, dt, 2, st);
+      if (e == hipSuccess) e = nlse_launch_pair2d(L, alt, g->psi, acc, u2, lo, dt, 1, st);
+      if (e == hipSuccess) e = nlse_launch_pair2d(L, alt, g->psi, acc, u2, lo, dt, 2, st);
+      if (e != hipSuccess) return e;
+    }
+  } else if (bc != NLSE_BC_L0 && fused_eligible(g->shape, g->dtype, g->flags, order) && tile[0] == 32 &&
+             tile[1] == 8) {
     // Pairs of steps Psi -> workspace -> Psi (the fused launches cannot
     // update Psi in place); an odd last step takes the four-pass kernels,
     // which give the same bits.
@@ -690,6 +714,8 @@ static std::vector<std::array<int, 3>> candidates(const nlse_grid* g, int order)
     // the whole-grid kernel replaces four launches per step by none: when
     // it fits it is the only candidate (its runs would change the field)
     out.push_back({s.npts <= nlse_resident1d_max_points(g->dtype) ? 1024 : 256, 1, 1});
+  } else if (s.ndim == 2 && pairs2d_eligible(s, g->flags)) {
+    for (auto t : {std::array<int, 3>{32, 32, 1}, {64, 16, 1}}) out.push_back(t);
   } else if (s.ndim == 2) {
     for (auto t : {std::array<int, 3>{32, 8, 1}, {64, 4, 1}, {64, 8, 1}}) out.push_back(t);
   } else if (fused_eligible(s, g->dtype, g->flags, order)) {
@@ -718,9 +744,9 @@ static std::vector<std::array<int, 3>> candidates(const nlse_grid* g, int order)
 
 static std::string cache_key(const nlse_grid* g, int order, int bc) {
   char buf[160];
-  snprintf(buf, sizeof buf, "d%d n%lldx%lldx%lld t%d o%d b%d c%d v%d", g->shape.ndim, (long long)g->shape.n[0],
+  snprintf(buf, sizeof buf, "d%d n%lldx%lldx%lld t%d o%d b%d c%d v%d p%d", g->shape.ndim, (long long)g->shape.n[0],
            (long long)g->shape.n[1], (long long)g->shape.n[2], g->dtype, order, bc,
-           (g->flags & NLSE_COMPENSATED) ? 1 : 0, g->V ? 1 : 0);
+           (g->flags & NLSE_COMPENSATED) ? 1 : 0, g->V ? 1 : 0, (g->flags & NLSE_FUSED_PAIRS) ? 1 : 0);
   return buf;
 }
 
@@ -766,8 +792,8 @@ void nlse_cache_store(const std::string& key, const int* t, int n, float ms) {
 }
 
 // Times stages 1-3 only (they read Psi but never write it), or the first
-// fused pair (stages 1+2), so the field is left untouched; the accumulator
-// and stage buffers are scratch.
+// fused pair (stages 1+2) of fused 3D and stage-pair 2D grids, so the field
+// is left untouched; the accumulator and stage buffers are scratch.
 extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   if (!g) return fail(NLSE_EINVAL, "g is NULL");
   int rc = check_scheme(order, bc);
@@ -811,9 +837,17 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   std::array<int, 3> best_t = cands[0];
   const int reps = g->shape.npts > (1 << 20) ? 5 : 20;
   const bool fused = bc != NLSE_BC_L0 && fused_eligible(g->shape, g->dtype, g->flags, order);
+  const bool pairs2d = pairs2d_eligible(g->shape, g->flags);
   for (auto& t : cands) {
     for (int d = 0; d < 3; ++d) L.tile[d] = t[d];
     auto run = [&](int n) -> hipError_t {
+      if (pairs2d) {
+        for (int r = 0; r < n; ++r) {
+          hipError_t ee = nlse_launch_pair2d(L, g->psi, B, L.acc, A, nullptr, dt, 1, g->stream);
+          if (ee != hipSuccess) return ee;
+        }
+        return hipSuccess;
+      }
       if (fused) {
         for (int r = 0; r < n; ++r) {
           hipError_t ee = nlse_launch_fused3d_pair0(L, g->psi, L.acc, A, dt, g->stream);

@@ -60,6 +60,11 @@ hipError_t nlse_launch_fused3d(const nlse::StageLaunch& L, const void* psi_in, v
 // Only the first fused launch (reads psi, writes acc and mid): for timing.
 hipError_t nlse_launch_fused3d_pair0(const nlse::StageLaunch& L, const void* psi, void* acc, void* mid, double dt,
                                      hipStream_t st);
+// One stage pair of a 2D grid (pair 1: stages 1+2 from psi_in into acc and
+// u2 = U2; pair 2: stages 3+4 from u2 into psi_out and lo); psi_out must not
+// be psi_in.  L.tile = 32x32 or 64x16 (hipErrorInvalidValue otherwise).
+hipError_t nlse_launch_pair2d(const nlse::StageLaunch& L, const void* psi_in, void* psi_out, void* acc, void* u2,
+                              void* lo, double dt, int pair, hipStream_t st);
 hipError_t nlse_launch_reduce(const nlse::ReduceLaunch& R, hipStream_t st);
 // Device addresses, on the current device, of the library's static reduction
 // scratch: kStaticReduceBlocks * 3 partial doubles and 3 result doubles

@@ -124,6 +124,36 @@ def test_fused_pairs_equal_four_passes(shape, bc, comp, withV, cz):
     assert rel_l2(fused, ref) < TOL["f32"]
 
 
+PAIRS2D_CASES = [((37, 70), 4, "msd", "f32", True, True, (32, 32, 1), 7),
+                 ((37, 70), 4, "dirichlet", "f32", False, False, (64, 16, 1), 6),
+                 ((3, 3), 4, "msd", "f32", True, False, (32, 32, 1), 5),
+                 ((130, 9), 2, "l0", "f32", True, True, (64, 16, 1), 7),
+                 ((66, 200), 4, "l0", "f64", False, True, (32, 32, 1), 5),
+                 ((66, 200), 2, "msd", "f64", False, False, (64, 16, 1), 4),
+                 ((5, 67), 2, "dirichlet", "f32", False, True, (32, 32, 1), 3),
+                 ((100, 100), 4, "msd", "f32", True, True, (64, 16, 1), 9),
+                 ((129, 47), 4, "dirichlet", "f64", False, True, (64, 16, 1), 1)]
+
+
+@pytest.mark.parametrize("shape,order,bc,dtype,comp,withV,tile,n", PAIRS2D_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-o{c[1]}-{c[2]}-{c[3]}-c{int(c[4])}-v{int(c[5])}-"
+                              f"{c[6][0]}x{c[6][1]}-n{c[7]}" for c in PAIRS2D_CASES])
+def test_pairs2d_equal_four_passes(shape, order, bc, dtype, comp, withV, tile, n):
+    """2D grids with NLSE_FUSED_PAIRS (two stage-pair launches per step,
+    Psi alternating with a workspace array over pairs of steps, an odd last
+    step in four passes): the bits of the four single-stage launches with
+    the same tile, for both schemes, every boundary condition and type, tiny
+    and ragged shapes; within the tolerance of the oracle."""
+    u, V, h, a, s = smooth_problem(shape, 80 + n, V=withV)
+    dt = 0.5 * oracle.dt_max(2, order, h, a)
+    pairs = run_gpu(u, h, a, s, dt, n, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=tile,
+                    fused_pairs=True)
+    four = run_gpu(u, h, a, s, dt, n, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=tile)
+    assert np.array_equal(pairs, four)
+    ref = oracle.rk4(u, h, a, s, dt, n, V=V, order=order, bc=bc)
+    assert rel_l2(pairs, ref) < TOL[dtype]
+
+
 RES_CASES = [(n, dt, o, bc, c) for (n, dt) in ((3, "f64"), (600, "f64"), (1024, "f64"), (1030, "f32"), (2048, "f32"))
              for o, bc in ((2, "dirichlet"), (4, "msd"), (4, "l0"), (2, "msd")) for c in ((False, True) if dt == "f32" else (False,))]
 
@@ -287,6 +317,29 @@ def test_autotune_keeps_field_and_bits():
     ref = run_gpu(u, h, a, s, dt, 5, V=V, order=4, bc="msd", dtype="f32", compensated=True,
                   tile=(64, 4, 8))
     assert np.array_equal(tuned.astype(np.complex128), ref)
+
+
+def test_autotune_pairs2d_keeps_field_and_picks_a_pair_tile():
+    """On a 2D grid with stage pairs the autotuner chooses between the pair
+    tiles (timing the first pair launch only), leaves the field as it was,
+    and the tuned run equals a four-pass run."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem((70, 150), 13)
+    dt = 0.5 * oracle.dt_max(2, 4, h, a)
+    psi = to_dev(u, "f32")
+    before = psi.clone()
+    g = Grid(psi, h, a, s, V=pot_dev(V, "f32"), compensated=True, fused_pairs=True)
+    g.autotune(4, "msd", dt)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, before)
+    assert tuple(g.tile(4)) in ((32, 32, 1), (64, 16, 1))
+    g.step(dt, 6, order=4, bc="msd")
+    tuned = psi.cpu().numpy()
+    ref = run_gpu(u, h, a, s, dt, 6, V=V, order=4, bc="msd", dtype="f32", compensated=True, tile=(64, 4, 1))
+    assert np.array_equal(tuned.astype(np.complex128), ref)
+    g.close()
 
 
 def test_checkpoint_restore_bitwise():
