@@ -15,6 +15,10 @@ hipError_t nlse_launch_fused3d(const nlse::StageLaunch&, const void*, void*, voi
                                hipStream_t) {
   return hipErrorNotSupported;
 }
+hipError_t nlse_launch_pair2d(const nlse::StageLaunch&, const void*, void*, void*, void*, void*, double, int,
+                              hipStream_t) {
+  return hipErrorNotSupported;
+}
 hipError_t nlse_launch_fused3d_pair0(const nlse::StageLaunch&, const void*, void*, void*, double, hipStream_t) {
   return hipErrorNotSupported;
 }
