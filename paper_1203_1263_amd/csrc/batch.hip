@@ -217,7 +217,9 @@ __device__ __forceinline__ PairItem<T> decode_pair(const BatchArgs<T>& B, unsign
 // waiting for it later must not mean waiting for them.  Past the end of the
 // chunk the last item is loaded again (and not computed), which keeps the
 // memory operations straight-line code.  `compute` gets the LDS buffer
-// parity of the item (consecutive items alternate).
+// parity of the item (consecutive items alternate), the next item's
+// arguments and registers (its loads in flight) and whether it exists and
+// whether the item is the first of the chunk.
 template <typename Regs, typename Dec, typename Issue, typename Compute>
 __device__ __forceinline__ void run_items(const BatchItem* items, int i0, int i1, Dec dec, Issue issue,
                                           Compute compute) {
@@ -228,7 +230,7 @@ __device__ __forceinline__ void run_items(const BatchItem* items, int i0, int i1
     wc = words(it + 2);
     __builtin_amdgcn_sched_barrier(0);
     issue(Inxt, nxt);
-    compute(Icur, cur, buf);
+    compute(Icur, cur, buf, Inxt, nxt, it + 1 < i1, it == i0);
   };
   if (i0 >= i1) return;
   unsigned wa = words(i0), wb = words(i0 + 1);
@@ -253,15 +255,17 @@ struct BatchLds {
 };
 
 // LDS of a stage pair: input and potential box with the 2SHOC pair halo of
-// 4 (alternating between items), the first stage's D box (the second
-// stage's D is smaller and reuses it) and the first stage's output on the
-// tile and its ring of 2.
+// 4 and the first stage's D box (the second stage's D is smaller and
+// reuses it), alternating between consecutive items, and the first stage's
+// output on the tile and its ring of 2.  An item stores the next item's box
+// before its own last barrier, so the next item's first D pass may run
+// while slower waves still finish this item's second stage.
 template <typename T, int TX, int TY>
 struct PairLds {
   static constexpr int BSZ = (TX + 8) * (TY + 8);
   cpx<T> u[2][BSZ];
   T v[2][BSZ];
-  cpx<T> d[(TX + 6) * (TY + 6)];
+  cpx<T> d[2][(TX + 6) * (TY + 6)];
   cpx<T> m[(TX + 4) * (TY + 4)];
 };
 
@@ -276,7 +280,7 @@ __device__ __forceinline__ void batch_stage(const BatchArgs<T>& B, int i0, int i
     else
       tile2d_load<T, STAGE, COMP, TX, TY, 1, true>(I.A, I.tx, I.ty, r);
   };
-  auto compute = [&](const ItemArgs<T>& I, const Regs& r, int buf) {
+  auto compute = [&](const ItemArgs<T>& I, const Regs& r, int buf, const ItemArgs<T>&, const Regs&, bool, bool) {
     cpx<T>* sU = S.u[buf];
     T* sV = S.v[buf];
     if (I.order == 4)
@@ -300,13 +304,24 @@ __device__ __forceinline__ void batch_pair(const BatchArgs<T>& B, int i0, int i1
     else
       pair2d_load<T, PAIR, COMP, TX, TY, 1, true>(I.A, I.tx, I.ty, r);
   };
-  auto compute = [&](const PairItem<T>& I, const Regs& r, int buf) {
-    cpx<T>* sU = S.u[buf];
-    T* sV = S.v[buf];
+  auto compute = [&](const PairItem<T>& I, const Regs& r, int buf, const PairItem<T>& In, const Regs& rn,
+                     bool has_next, bool first) {
+    // the first item of the chunk stores its own box; every item stores the
+    // next one's (with that item's halo) into the other buffers
+    auto before_last = [&] {
+      if (has_next) {
+        if (In.order == 4)
+          pair2d_put<T, TX, TY, 2>(rn, S.u[buf ^ 1], S.v[buf ^ 1]);
+        else
+          pair2d_put<T, TX, TY, 1>(rn, S.u[buf ^ 1], S.v[buf ^ 1]);
+      }
+    };
     if (I.order == 4)
-      pair2d_compute<T, 4, kAnyBC, PAIR, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d, S.m, I.bc);
+      pair2d_compute<T, 4, kAnyBC, PAIR, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, S.u[buf], S.v[buf], S.d[buf],
+                                                             S.m, I.bc, !first, before_last);
     else
-      pair2d_compute<T, 2, kAnyBC, PAIR, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, sU, sV, S.d, S.m, I.bc);
+      pair2d_compute<T, 2, kAnyBC, PAIR, COMP, TX, TY, true>(I.A, I.tx, I.ty, r, S.u[buf], S.v[buf], S.d[buf],
+                                                             S.m, I.bc, !first, before_last);
   };
   run_items<Regs>(B.items, i0, i1, dec, issue, compute);
 }

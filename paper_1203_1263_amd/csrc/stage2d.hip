@@ -54,7 +54,8 @@ __global__ __launch_bounds__(TX* TY) void pair2d_kernel(PairArgs<T> A, int bc) {
   const int t = xcd_swizzle(blockIdx.x, gridDim.x);
   PairRegs<T, TX, TY> R;
   pair2d_load<T, PAIR, COMP, TX, TY, H, STREAM>(A, t % ntx, t / ntx, R);
-  pair2d_compute<T, ORDER, kAnyBC, PAIR, COMP, TX, TY, STREAM>(A, t % ntx, t / ntx, R, sU, sV, sD, sM, bc);
+  pair2d_compute<T, ORDER, kAnyBC, PAIR, COMP, TX, TY, STREAM>(A, t % ntx, t / ntx, R, sU, sV, sD, sM, bc, false,
+                                                                [] {});
 }
 
 template <typename T, int COMP>

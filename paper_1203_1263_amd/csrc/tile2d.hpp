@@ -367,18 +367,38 @@ __device__ __forceinline__ void pair2d_load(const PairArgs<T>& A, int tx, int ty
   }
 }
 
+// The input and potential box of a pair with first-stage halo H (box halo
+// 2H) from the loads in R into LDS.
+template <typename T, int TX, int TY, int H>
+__device__ __forceinline__ void pair2d_put(const PairRegs<T, TX, TY>& R, cpx<T>* __restrict__ sU,
+                                           T* __restrict__ sV) {
+#pragma unroll
+  for (int k = 0; k < box_pf<TX, TY, 2 * H>(); ++k) {
+    const int i = box_elem<TX, TY, 2 * H>(k);
+    sU[i] = R.u[k];
+    sV[i] = R.v[k];
+  }
+}
+
 // Pair PAIR of tile (tx, ty) from the loads in R.  sU, sV hold the input and
 // potential box (halo 2H), sD the D box of either stage ((TY+2H+2)(TX+2H+2)
 // elements), sM the first stage's output on the tile and its H ring.
-// Contains barriers: every thread of the workgroup must call it.  As in
-// tile2d_compute, the first barrier orders this call's writes of sU and sV
-// after earlier reads only through the caller; sD and sM are written after
-// it.
-template <typename T, int ORDER, int BC, int PAIR, int COMP, int TX, int TY, bool STREAM = false>
+// Contains barriers: every thread of the workgroup must call it.
+// Unless box_in_lds (the caller stored this tile's box and made it visible
+// with a barrier), the box is stored from R first and a barrier follows; as
+// in tile2d_compute, that barrier orders the stores after earlier reads of
+// sU and sV only through the caller.  before_last() runs once in every
+// thread just before the last barrier, after every write of sD and sM: a
+// caller that alternates sU, sV and sD between consecutive items stores the
+// next item's box into the other sU and sV there, and the next item (if
+// 2SHOC) starts its first D pass, into the other sD, without a barrier.  sM
+// is written only after a barrier of the item (its D barrier for 2SHOC, a
+// first barrier kept for CD2), so one sM serves consecutive items.
+template <typename T, int ORDER, int BC, int PAIR, int COMP, int TX, int TY, bool STREAM = false, class Before>
 __device__ __forceinline__ void pair2d_compute(const PairArgs<T>& A, int tx, int ty, const PairRegs<T, TX, TY>& R,
                                                cpx<T>* __restrict__ sU, T* __restrict__ sV,
-                                               cpx<T>* __restrict__ sD, cpx<T>* __restrict__ sM,
-                                               int rt_bc = kAnyBC) {
+                                               cpx<T>* __restrict__ sD, cpx<T>* __restrict__ sM, int rt_bc,
+                                               bool box_in_lds, Before&& before_last) {
   const int bc = BC == kAnyBC ? rt_bc : BC;
   constexpr int NT = TX * TY;
   constexpr int H = ORDER == 4 ? 2 : 1, G = 2 * H;
@@ -395,13 +415,8 @@ __device__ __forceinline__ void pair2d_compute(const PairArgs<T>& A, int tx, int
   const Phys<T>& ph = A.ph;
   const cpx<T> z = czero<T>();
 
-#pragma unroll
-  for (int k = 0; k < box_pf<TX, TY, G>(); ++k) {
-    const int i = box_elem<TX, TY, G>(k);
-    sU[i] = R.u[k];
-    sV[i] = R.v[k];
-  }
-  __syncthreads();
+  if (!box_in_lds) pair2d_put<T, TX, TY, H>(R, sU, sV);
+  if (!box_in_lds || ORDER == 2) __syncthreads();
 
   const LdsView<cpx<T>, BW> U{sU, x0 - G, y0 - G};
   const LdsView<T, BW> V{sV, x0 - G, y0 - G};
@@ -453,12 +468,12 @@ __device__ __forceinline__ void pair2d_compute(const PairArgs<T>& A, int tx, int
         sM[r * RW + c] = m;
       }
     }
-    __syncthreads();
-
     if constexpr (ORDER == 4) {
-      d_box<T, IN, NT, TX + 2, TY + 2>(ph, M, V, sD, x0 - 1, y0 - 1, nx, ny, bc);
       __syncthreads();
+      d_box<T, IN, NT, TX + 2, TY + 2>(ph, M, V, sD, x0 - 1, y0 - 1, nx, ny, bc);
     }
+    before_last();
+    __syncthreads();
     if (store) {
       const cpx<T> K = k_at<T, ORDER, IN>(ph, M, V, D2, x, y, nx, ny, bc);
       Own<T> o;
