@@ -68,6 +68,7 @@ def generate(ntraj: int, npairs: int = 100, burn: int = 160, seed_index: int = 4
     probs = [_P(wl.surrogate_ic(g, N, H_STEP)) for _ in range(ntraj)]
     dt = dt_default()
     b = Batch(probs, [dt] * ntraj, compensated=True)
+    b.autotune()  # any configuration gives the same bits; this one is fastest
     snaps = torch.empty((ntraj, npairs + 1, N, N), dtype=torch.complex64, device="cuda")
     pool = b.pool.view(ntraj, N, N)
     b.step(burn)
@@ -205,7 +206,10 @@ def _time(fn, reps: int):
 
 def speedup(m, snaps, batch: int):
     """Time of one block (surrogate forward, MSD projection and mass check,
-    one library call) vs 16 RK4 steps."""
+    one library call) vs 16 RK4 steps of the fastest integrator
+    configuration: at batch 1 the faster of an autotuned four-pass grid and
+    an autotuned stage-pair grid, at larger batches the autotuned batched
+    integrator (tile, grid size, four passes or stage pairs)."""
     import torch
     dt = dt_default()
     fields = snaps[:batch, 0].contiguous()
@@ -215,23 +219,35 @@ def speedup(m, snaps, batch: int):
         m.block(fields, out)  # forward, MSD projection and masses in one pass (synchronises)
 
     if batch == 1:
-        psi = fields[0].clone()
-        g = Grid(psi, H_STEP, A, S_NL, compensated=True)
+        t_rk, rk_config = None, None
+        for pairs in (False, True):
+            psi = fields[0].clone()
+            g = Grid(psi, H_STEP, A, S_NL, compensated=True, fused_pairs=pairs)
+            g.autotune(4, "msd", dt)
 
-        def rk4_block():
-            g.step(dt, BLOCK, order=4, bc="msd")
+            def rk4_block():
+                g.step(dt, BLOCK, order=4, bc="msd")
+            t = _time(rk4_block, 10)
+            if t_rk is None or t < t_rk:
+                t_rk, rk_config = t, {"stage_pairs": pairs, "tile": list(g.tile(4))}
+            g.close()
     else:
         probs = [_P(fields[i].cpu().numpy()) for i in range(batch)]
         b = Batch(probs, [dt] * batch, compensated=True)
+        b.autotune()
 
         def rk4_block():
             b.step(BLOCK)
-    t_rk = _time(rk4_block, 10)
+        t_rk = _time(rk4_block, 10)
+        tx, ty, wg, pairs = b.config()
+        rk_config = {"stage_pairs": bool(pairs), "tile": [tx, ty], "wg_per_cu": wg}
+        b.close()
     t_sg = _time(surrogate_block, 10)
     t_fwd = _time(lambda: m.forward(fields, out), 10)
     fwd_flop = FLOP_PER_PIXEL * batch * N * N
     fwd_bytes = BYTES_PER_PIXEL * batch * N * N
-    return {"batch": batch, "ms_rk4_16_steps": t_rk, "ms_surrogate_block": t_sg, "speedup": t_rk / t_sg,
+    return {"batch": batch, "ms_rk4_16_steps": t_rk, "rk4_config": rk_config, "ms_surrogate_block": t_sg,
+            "speedup": t_rk / t_sg,
             "ms_forward": t_fwd, "forward_tflops": fwd_flop / (t_fwd * 1e-3) / 1e12,
             "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9}
 
