@@ -12,6 +12,12 @@
 // loads with the previous tile's arithmetic: tile2d_load issues every global
 // load of a tile into registers (straight-line code: each address is clamped
 // into the grid), tile2d_compute consumes them.  Loads are coalesced along x.
+//
+// The per-point pieces (d_at, k_at, and stage_values in nlse_device.hpp)
+// also make up the stage-pair body further down (pair2d_load /
+// pair2d_compute: two RK4 stages per pass, the first on the tile and its
+// halo ring), so one stage, two stages per pass and a batch all give the
+// same bits.
 #pragma once
 
 #include <type_traits>

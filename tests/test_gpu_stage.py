@@ -150,6 +150,10 @@ def test_pairs2d_equal_four_passes(shape, order, bc, dtype, comp, withV, tile, n
                     fused_pairs=True)
     four = run_gpu(u, h, a, s, dt, n, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=tile)
     assert np.array_equal(pairs, four)
+    if n == 7:  # direct launches (no graph) give the same bits
+        direct = run_gpu(u, h, a, s, dt, n, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=tile,
+                         fused_pairs=True, graph=False)
+        assert np.array_equal(direct, four)
     ref = oracle.rk4(u, h, a, s, dt, n, V=V, order=order, bc=bc)
     assert rel_l2(pairs, ref) < TOL[dtype]
 
