@@ -155,8 +155,9 @@ def test_autotune_keeps_fields_and_caches_its_choice(tmp_path, monkeypatch):
         x.close()
 
 
+@pytest.mark.parametrize("tile", [(64, 8, 2), (32, 32, 1), (64, 16, 1)], ids=["64x8-w2", "32x32-w1", "64x16-w1"])
 @pytest.mark.parametrize("dtype,comp", [("f32", False), ("f64", False), ("f32", True)])
-def test_stage_pairs_equal_four_passes_in_every_mode(dtype, comp):
+def test_stage_pairs_equal_four_passes_in_every_mode(dtype, comp, tile):
     """Two stage-pair passes per step give the bits of four single-stage
     passes (same tile), in every element type and mode, for calls of 1, 2
     and 3 steps (Psi alternates with a work buffer inside a call and must be
@@ -167,8 +168,8 @@ def test_stage_pairs_equal_four_passes_in_every_mode(dtype, comp):
     for graph in (False, True):
         four = Batch(probs, dts, dtype=dtype, compensated=comp, graph=graph)
         two = Batch(probs, dts, dtype=dtype, compensated=comp, graph=graph)
-        four.set_config(64, 8, 2, False)
-        two.set_config(64, 8, 2, True)
+        four.set_config(tile[0], tile[1], tile[2], False)
+        two.set_config(tile[0], tile[1], tile[2], True)
         for n in (1, 2, 3):
             four.step(n)
             two.step(n)
