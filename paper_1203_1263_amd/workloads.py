@@ -266,6 +266,14 @@ def _gaussian_blur_noise(g, ny, nx, sigma_cells):
     return f / np.sqrt(np.mean(np.abs(f) ** 2))
 
 
+# Mass of the 2D ground state R of Laplacian(R) - R + R^3 = 0 (the Townes
+# profile), 2 pi int R^2 r dr: the critical mass of the focusing cubic NLSE in
+# 2D.  For i psi_t + a Lap psi + s |psi|^2 psi = 0 (s > 0) it scales to
+# TOWNES_MASS * a / s; below it solutions exist for all time, above it they
+# can collapse in finite time.
+TOWNES_MASS = 11.7008965
+
+
 def batch2d(nsims: int = 512, h: float = 0.25, nsteps: int = 500, index: int = 3,
             sizes=BATCH_SIZES) -> List[Problem]:
     """Independent 2D problems: Nx, Ny drawn independently from ``sizes``;
@@ -273,7 +281,11 @@ def batch2d(nsims: int = 512, h: float = 0.25, nsteps: int = 500, index: int = 3
     Gaussians with amplitudes U[-1, 1] and widths U[0.05, 0.2] L_min; IC =
     complex white noise blurred by a Gaussian of 4 cells (correlation length
     4h), unit RMS, times exp(-r^2 / 2 sigma_e^2), sigma_e = L_min/8, scaled to
-    max |psi|^2 = 1.  Zero-ish edges, so Dirichlet boundaries."""
+    max |psi|^2 = 1, and for focusing problems (s = +1) further down to at
+    most half the critical mass TOWNES_MASS * a / s, so no problem collapses
+    (above it the continuous solution can blow up in finite time, which an
+    explicit integrator cannot follow).  Zero-ish edges, so Dirichlet
+    boundaries."""
     g = rng(index)
     out = []
     for j in range(nsims):
@@ -294,6 +306,10 @@ def batch2d(nsims: int = 512, h: float = 0.25, nsteps: int = 500, index: int = 3
         se = Lmin / 8.0
         psi = psi * np.exp(-(X * X + Y * Y) / (2 * se * se))
         psi = psi / np.sqrt(np.max(np.abs(psi) ** 2))
+        if s > 0:
+            mass, cap = h * h * float(np.sum(np.abs(psi) ** 2)), 0.5 * TOWNES_MASS * a / s
+            if mass > cap:
+                psi = psi * np.sqrt(cap / mass)
         out.append(Problem(f"batch{j}", psi, h, a, s, V, order, "dirichlet", nsteps))
     return out
 

@@ -246,7 +246,9 @@ def test_batch_info_and_schedule():
 
 def test_c4_batch_512_problems_500_steps():
     """The 512-problem workload (uneven sizes 64..512, CD2/2SHOC, a, s, V per
-    problem), 500 steps in one launch, sampled against the FP64 oracle."""
+    problem), 500 steps in one launch: sampled against the FP64 oracle, every
+    problem's field finite at the end (mass and energy of all 512), and the
+    autotuner's configuration bitwise equal to the default one."""
     import torch
     from paper_1203_1263_amd.nlse import Batch
     path = os.path.join(GOLDEN, "c4_batch2d_512x500.npz")
@@ -267,3 +269,16 @@ def test_c4_batch_512_problems_500_steps():
         worst = max(worst, err)
         assert err < 1e-5, f"problem {j}: {err:.3e}"
     print(f"c4 worst sampled rel L2 {worst:.3e}")
+    M, E = b.mass_energy()  # raises if any problem's mass or energy is not finite
+    for j in G["sel"]:
+        assert M[int(j)] == pytest.approx(float(G[f"me{j}"][0]), rel=1e-5)
+    # the configuration the autotuner picks on this workload (32x32 stage
+    # pairs, one workgroup per CU) gives the same bits at full size
+    b2 = Batch(probs, dts, compensated=True)
+    b2.set_config(32, 32, 1, True)
+    b2.step(500)
+    b2.status()
+    torch.cuda.synchronize()
+    assert torch.equal(b.pool, b2.pool)
+    b.close()
+    b2.close()

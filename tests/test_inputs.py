@@ -91,3 +91,51 @@ def test_paper_ring_input():
     # the ring speed law: ln growth with radius, 1/d decay
     assert wl.ring_velocity(8.0, 1.0) < wl.ring_velocity(4.0, 1.0)
     assert wl.ring_velocity(4.0, 0.5) == pytest.approx(0.5 / 4.0 * (math.log(8 * 4.0) - 0.615))
+
+
+def test_townes_mass_constant():
+    """The critical mass used by the batch workload: the 2D ground state of
+    R'' + R'/r - R + R^3 = 0 (R'(0) = 0, R -> 0) found by shooting on R(0)
+    (too small: R turns back up; too large: R crosses zero), its mass
+    2 pi int R^2 r dr against TOWNES_MASS."""
+    from scipy.integrate import solve_ivp
+
+    def shoot(r0, rmax=12.0):
+        def f(r, y):
+            return [y[1], -y[1] / r + y[0] - y[0] ** 3]
+        r1 = 1e-6  # series start: R = r0 + (r0 - r0^3) r^2 / 4
+        y1 = [r0 + (r0 - r0 ** 3) * r1 * r1 / 4, (r0 - r0 ** 3) * r1 / 2]
+        cross = lambda r, y: y[0]
+        cross.terminal = True
+        turn = lambda r, y: y[1]
+        turn.terminal = True
+        turn.direction = 1
+        sol = solve_ivp(f, (r1, rmax), y1, rtol=1e-12, atol=1e-14, events=(cross, turn), dense_output=True)
+        return sol
+
+    lo, hi = 2.0, 2.5
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        sol = shoot(mid)
+        if sol.t_events[0].size:  # crossed zero: start too high
+            hi = mid
+        else:
+            lo = mid
+    sol = shoot(0.5 * (lo + hi), rmax=8.0)
+    r = np.linspace(1e-6, sol.t[-1], 20001)
+    R = sol.sol(r)[0]
+    mass = 2 * np.pi * np.trapezoid(R * R * r, r)
+    assert 2.20 < 0.5 * (lo + hi) < 2.21          # R(0) of the Townes profile
+    assert mass == pytest.approx(wl.TOWNES_MASS, rel=2e-4)
+
+
+def test_batch_focusing_problems_stay_below_half_the_critical_mass():
+    """Every focusing problem of the batched workload starts at or below half
+    the critical mass TOWNES_MASS * a / s (so none can collapse); the
+    defocusing ones keep max |psi|^2 = 1."""
+    for p in wl.batch2d():
+        mass = p.h * p.h * float(np.sum(np.abs(p.psi0) ** 2))
+        if p.s > 0:
+            assert mass <= 0.5 * wl.TOWNES_MASS * p.a / p.s * (1 + 1e-12)
+        else:
+            assert np.max(np.abs(p.psi0) ** 2) == pytest.approx(1.0)
