@@ -344,13 +344,42 @@ __device__ __forceinline__ void pair2d_load(const PairArgs<T>& A, int tx, int ty
   const int x0 = tile_origin(tx, TX, nx), y0 = tile_origin(ty, TY, ny);
   const int tid = threadIdx.x;
   constexpr int PF = box_pf<TX, TY, G>();
-  int off[PF];
+  constexpr int NR = ring_n<TX, TY, H>(), RP = (NR + NT - 1) / NT;
+  // A tile that takes the interior body of pair2d_compute (its first D
+  // pass stays H + 1 cells inside the edges) has its whole 2H box inside
+  // the grid, so its offsets need no clamping (uniform over the workgroup).
+  const bool in = x0 - H - 1 >= 1 && x0 + TX + H <= nx - 2 && y0 - H - 1 >= 1 && y0 + TY + H <= ny - 2;
+  int off[PF], roff[RP];
+  if (in) {
+    const int base = (y0 - G) * nx + (x0 - G);
 #pragma unroll
-  for (int k = 0; k < PF; ++k) {
-    const int i = box_elem<TX, TY, G>(k);
-    const int r = i / BW, c = i - r * BW;
-    const int gx = min(max(x0 - G + c, 0), nx - 1), gy = min(max(y0 - G + r, 0), ny - 1);
-    off[k] = gy * nx + gx;
+    for (int k = 0; k < PF; ++k) {
+      const int i = box_elem<TX, TY, G>(k);
+      const int r = i / BW, c = i - r * BW;
+      off[k] = base + r * nx + c;
+    }
+    const int rbase = (y0 - H) * nx + (x0 - H);
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      int r, c;
+      ring_pos<TX, TY, H>(min(tid + k * NT, NR - 1), r, c);
+      roff[k] = rbase + r * nx + c;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const int i = box_elem<TX, TY, G>(k);
+      const int r = i / BW, c = i - r * BW;
+      const int gx = min(max(x0 - G + c, 0), nx - 1), gy = min(max(y0 - G + r, 0), ny - 1);
+      off[k] = gy * nx + gx;
+    }
+#pragma unroll
+    for (int k = 0; k < RP; ++k) {
+      int r, c;
+      ring_pos<TX, TY, H>(min(tid + k * NT, NR - 1), r, c);
+      const int gx = min(max(x0 - H + c, 0), nx - 1), gy = min(max(y0 - H + r, 0), ny - 1);
+      roff[k] = gy * nx + gx;
+    }
   }
 #pragma unroll
   for (int k = 0; k < PF; ++k) R.u[k] = A.uin[off[k]];
@@ -362,14 +391,8 @@ __device__ __forceinline__ void pair2d_load(const PairArgs<T>& A, int tx, int ty
     R.own.psi = A.psi[i];
     R.own.acc = ld_own<T, STREAM>(A.acc + i);
     if constexpr (COMP) R.own.lo = ld_own<T, STREAM>(A.lo + i);
-    constexpr int NR = ring_n<TX, TY, H>();
 #pragma unroll
-    for (int k = 0; k < (NR + NT - 1) / NT; ++k) {
-      int r, c;
-      ring_pos<TX, TY, H>(min(tid + k * NT, NR - 1), r, c);
-      const int gx = min(max(x0 - H + c, 0), nx - 1), gy = min(max(y0 - H + r, 0), ny - 1);
-      R.rpsi[k] = A.psi[gy * nx + gx];
-    }
+    for (int k = 0; k < RP; ++k) R.rpsi[k] = A.psi[roff[k]];
   }
 }
 
