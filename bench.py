@@ -68,7 +68,7 @@ def parse():
                     help="ring3d: 3D GPE at n^3 (default); batch2d: 512 uneven 2D problems in one launch; "
                          "surrogate: train the 16-step surrogate and time it against RK4")
     ap.add_argument("--trajectories", type=int, default=200, help="surrogate: trajectories of 100 pairs")
-    ap.add_argument("--iters", type=int, default=16000, help="surrogate: Adam iterations")
+    ap.add_argument("--iters", type=int, default=32000, help="surrogate: Adam iterations")
     ap.add_argument("--cpu-child", type=int, default=0, help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")

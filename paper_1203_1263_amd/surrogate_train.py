@@ -1,6 +1,6 @@
 """Train and evaluate the convolutional surrogate of 16 RK4 steps.
 
-    python -m paper_1203_1263_amd.surrogate_train [--trajectories 200] [--iters 16000]
+    python -m paper_1203_1263_amd.surrogate_train [--trajectories 200] [--iters 32000]
 
 Workload: 2D defocusing NLSE on 256^2 (h = 0.25, a = 1, s = -1, V = 0, MSD
 boundaries, 2SHOC, FP32 with compensation, dt = 0.8 of the linear bound).
@@ -252,7 +252,7 @@ def speedup(m, snaps, batch: int):
             "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9}
 
 
-def run(ntraj: int = 200, iters: int = 16000, batch: int = 32, lr: float = 1e-3, seed: int = 0,
+def run(ntraj: int = 200, iters: int = 32000, batch: int = 32, lr: float = 1e-3, seed: int = 0,
         pushforward: float = 0.0):
     import torch
     t0 = time.perf_counter()
@@ -281,7 +281,7 @@ def run(ntraj: int = 200, iters: int = 16000, batch: int = 32, lr: float = 1e-3,
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trajectories", type=int, default=200)
-    ap.add_argument("--iters", type=int, default=16000)
+    ap.add_argument("--iters", type=int, default=32000)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--pushforward", type=float, default=0.0)
