@@ -428,6 +428,24 @@ def test_c2_full_size_short_run_full_field():
     assert rel_l2(got, ref) < TOL["f32"]
 
 
+def test_c2_stage_pairs_full_size_equal_four_passes_and_oracle():
+    """1024^2 vortex field, FP32 compensated, 1000 steps with stage pairs
+    (NLSE_FUSED_PAIRS, autotuned pair tile): the bits of the four-pass run
+    with the same tile, and the sampled oracle values within 1e-5."""
+    G = _golden("c2_vortex2d_1024x1024_1000")
+    p = wl.vortex2d(n=1024)
+    dt = p.dt_fraction * oracle.dt_max(2, p.order, p.h, p.a)
+    assert dt == float(G["dt"])
+    pairs, g = run_gpu(p.psi0, p.h, p.a, p.s, dt, 1000, order=4, bc="msd", dtype="f32", compensated=True,
+                       autotune=True, fused_pairs=True, return_grid=True)
+    tile = tuple(g.tile(4))
+    g.close()
+    assert tile in ((32, 32, 1), (64, 16, 1))
+    four = run_gpu(p.psi0, p.h, p.a, p.s, dt, 1000, order=4, bc="msd", dtype="f32", compensated=True, tile=tile)
+    assert np.array_equal(pairs, four)
+    assert rel_l2(pairs.reshape(-1)[G["idx"]], G["val"]) < TOL["f32"]
+
+
 def _golden(name):
     path = os.path.join(GOLDEN, name + ".npz")
     if not os.path.exists(path):
