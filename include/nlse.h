@@ -393,6 +393,27 @@ int nlse_surrogate_advance(nlse_surrogate *m, nlse_grid *g, int order, int bc,
                            double dt, int64_t nblocks, double drift_tol,
                            int64_t *n_fallbacks);
 
+/* Which kernels evaluate the network in nlse_surrogate_forward,
+ * nlse_surrogate_block and nlse_surrogate_advance (training always uses the
+ * layer-by-layer kernels, whose activations the backward pass reads):
+ *   NLSE_SG_PATH_AUTO   whole-network pass for batches of at most
+ *                       nlse_surrogate_fused_max_batch fields, else layers;
+ *   NLSE_SG_PATH_LAYERS one kernel per layer, activations through HBM;
+ *   NLSE_SG_PATH_FUSED  one kernel for all six layers: each workgroup takes a
+ *                       16 x 16 output tile through every layer with the
+ *                       activations in LDS, recomputing a ring of up to 5
+ *                       pixels per layer (1.8x the flops, no activation
+ *                       traffic, one launch).
+ * Both paths give the same bits (the same operands, MFMAs and epilogue
+ * operations in the same order).  Default: AUTO. */
+#define NLSE_SG_PATH_AUTO 0
+#define NLSE_SG_PATH_LAYERS 1
+#define NLSE_SG_PATH_FUSED 2
+int nlse_surrogate_set_path(nlse_surrogate *m, int path);
+/* Largest batch that NLSE_SG_PATH_AUTO sends through the whole-network
+ * kernel for this model's H x W. */
+int nlse_surrogate_fused_max_batch(const nlse_surrogate *m);
+
 int nlse_surrogate_destroy(nlse_surrogate *m);
 
 #ifdef __cplusplus

@@ -33,6 +33,9 @@ constexpr int kWgradParts = 512;
 constexpr int kLossParts = 1024;
 constexpr int kMassChunks = 64;
 constexpr int kBlockSteps = 16;  // RK4 steps one surrogate block stands for
+// NLSE_SG_PATH_AUTO: the whole-network kernel while a batch has at most this
+// many 16x16 tiles per CU (one workgroup per CU at a time)
+constexpr int kFusedTilesPerCU = 2;
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -119,6 +122,7 @@ struct nlse_surrogate {
   // training updates them in place
   hipStream_t cap = nullptr;
   std::map<std::tuple<const void*, void*, int, int>, hipGraphExec_t> graphs;
+  int path = NLSE_SG_PATH_AUTO;  // inference kernels
 };
 
 static void drop_graphs(nlse_surrogate* m) {
@@ -238,12 +242,58 @@ static int check_batch(nlse_surrogate* m, int batch) {
   return NLSE_OK;
 }
 
-// Forward pass of `batch` fields; activations stay in the workspace.  With
-// `checked`, the last layer also projects the boundary ring to the input's
-// modulus (project) and sums |psi_out|^2 per tile, and the field masses go to
-// the workspace (mout).
+// Compute units of the current device (queried once per process).
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) ==
+                                                 hipSuccess && n > 0)
+      cus = n;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Largest batch that NLSE_SG_PATH_AUTO sends through the whole-network kernel.
+static int fused_max_batch(const nlse_surrogate* m) {
+  const int tiles = (m->H / 16) * (m->W / 16);
+  return std::max(1, (kFusedTilesPerCU * device_cus()) / tiles);
+}
+
+static bool use_fused(const nlse_surrogate* m, int batch) {
+  return m->path == NLSE_SG_PATH_FUSED || (m->path == NLSE_SG_PATH_AUTO && batch <= fused_max_batch(m));
+}
+
+// Forward pass of `batch` fields.  With `checked`, the last layer also
+// projects the boundary ring to the input's modulus (project) and sums
+// |psi_out|^2 per tile, and the field masses go to the workspace (mout).
+// Training passes (`infer` false) run layer by layer and leave every
+// activation in the workspace for the backward pass; inference may take the
+// whole-network kernel instead.
 static hipError_t forward(nlse_surrogate* m, const void* psi_in, void* psi_out, int batch, bool checked = false,
-                          bool project = false) {
+                          bool project = false, bool infer = false) {
+  if (infer && use_fused(m, batch)) {
+    SgNet c;
+    std::memset(&c, 0, sizeof c);
+    c.x = psi_in;
+    c.pred = psi_out;
+    for (int l = 0; l < kNL; ++l) {
+      c.w[l] = U16(m, m->lay.wf[l]);
+      c.bias[l] = m->params + m->L[l].boff;
+    }
+    c.B = batch;
+    c.H = m->H;
+    c.W = m->W;
+    c.project = checked && project ? 1 : 0;
+    c.tile_mass = checked ? F64(m, m->lay.tmass) : nullptr;
+    hipError_t e = sg_net_forward(c, m->stream);
+    if (e == hipSuccess && checked)
+      e = sg_tile_mass_final(F64(m, m->lay.tmass), batch, (m->H / 16) * (m->W / 16), m->h * m->h,
+                             F64(m, m->lay.mout), m->stream);
+    return e;
+  }
   const int64_t P = (int64_t)batch * m->H * m->W;
   hipError_t e = sg_pack_input(psi_in, m->work + m->lay.x8, P, m->stream);
   for (int l = 0; l < kNL && e == hipSuccess; ++l) {
@@ -280,7 +330,7 @@ extern "C" int nlse_surrogate_forward(nlse_surrogate* m, const void* psi_in, voi
   // and mass check 0.121 -> 0.114 ms), though back-to-back passes overlap
   // direct launches slightly better (0.069 vs 0.077 ms each)
   hipError_t e = replay(m, std::make_tuple(psi_in, psi_out, batch, 0),
-                        [&]() { return forward(m, psi_in, psi_out, batch); });
+                        [&]() { return forward(m, psi_in, psi_out, batch, false, false, true); });
   return e == hipSuccess ? NLSE_OK : nlse_hip_fail(e, "surrogate forward");
 }
 
@@ -385,7 +435,7 @@ extern "C" int nlse_surrogate_block(nlse_surrogate* m, const void* psi_in, void*
   if (!mass) return nlse_fail(NLSE_EINVAL, "mass is NULL");
   const bool project = project_msd != 0;
   hipError_t e = replay(m, std::make_tuple(psi_in, psi_out, batch, project ? 4 : 3),
-                        [&]() { return forward(m, psi_in, psi_out, batch, true, project); });
+                        [&]() { return forward(m, psi_in, psi_out, batch, true, project, true); });
   if (e != hipSuccess) return nlse_hip_fail(e, "surrogate block");
   return fetch_masses(m, batch, mass);
 }
@@ -428,7 +478,7 @@ extern "C" int nlse_surrogate_advance(nlse_surrogate* m, nlse_grid* g, int order
   // the new field's mass, all in the last layer's pass (captured)
   auto block = [&]() {
     hipError_t e = nlse_launch_copy(xin, psi, (int64_t)bytes, m->stream);
-    if (e == hipSuccess) e = forward(m, xin, psi, 1, true, bc == NLSE_BC_MSD);
+    if (e == hipSuccess) e = forward(m, xin, psi, 1, true, bc == NLSE_BC_MSD, true);
     return e;
   };
   for (int64_t k = 0; k < nblocks; ++k) {
@@ -450,6 +500,20 @@ extern "C" int nlse_surrogate_advance(nlse_surrogate* m, nlse_grid* g, int order
   }
   if (n_fallbacks) *n_fallbacks = fb;
   return NLSE_OK;
+}
+
+extern "C" int nlse_surrogate_set_path(nlse_surrogate* m, int path) {
+  if (!m) return nlse_fail(NLSE_EINVAL, "m is NULL");
+  if (path != NLSE_SG_PATH_AUTO && path != NLSE_SG_PATH_LAYERS && path != NLSE_SG_PATH_FUSED)
+    return nlse_fail(NLSE_EINVAL, "path must be NLSE_SG_PATH_AUTO, _LAYERS or _FUSED");
+  if (path != m->path) drop_graphs(m);  // captured passes name their kernels
+  m->path = path;
+  return NLSE_OK;
+}
+
+extern "C" int nlse_surrogate_fused_max_batch(const nlse_surrogate* m) {
+  if (!m) return nlse_fail(NLSE_EINVAL, "m is NULL");
+  return fused_max_batch(m);
 }
 
 extern "C" int nlse_surrogate_destroy(nlse_surrogate* m) {

@@ -20,7 +20,20 @@ struct SgConv {
   double* tile_mass;     // last layer, or null: per 16x16 tile, sum of |pred|^2
 };
 
+// All six forward layers in one pass per 16x16 tile (inference only: no
+// activations are stored).
+struct SgNet {
+  const void* x;             // network input fields, complex64 [B][H][W]
+  void* pred;                // prediction, complex64
+  const uint16_t* w[6];      // BF16 forward-layout weights per layer
+  const float* bias[6];      // FP32 biases per layer
+  int B, H, W;
+  int project;               // MSD projection of the boundary ring
+  double* tile_mass;         // or null: per 16x16 tile, sum of |pred|^2
+};
+
 hipError_t sg_pack_input(const void* psi, void* x, int64_t n, hipStream_t st);
+hipError_t sg_net_forward(const SgNet& c, hipStream_t st);
 hipError_t sg_conv(int kind, const SgConv& c, hipStream_t st);
 hipError_t sg_loss(const void* pred, const void* tgt, uint16_t* dz, double* partial, int nparts, int64_t n,
                    hipStream_t st);

@@ -258,6 +258,323 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, in
   }
 }
 
+// ---------------------------------------------------------------- whole network, small batches
+
+// Inference for small batches: one workgroup takes one 16x16 output tile
+// through all six layers, with the activations in LDS instead of HBM.  Layer
+// l (1..6) is evaluated on the tile plus a ring of 6 - l pixels (26^2, 24^2,
+// ..., 16^2 pixels), which is exactly what the layers after it read; ring
+// pixels outside the image are stored as zero, the padding the layer-by-layer
+// pass applies.  Activations are stored channel-chunk major
+// ([ci / 8][pixel][8 values]), so the 16 lanes of an operand read take 256
+// contiguous bytes (no bank conflicts without padding, which would not fit:
+// weights 42 KB + the two largest regions 117 KB).  Every accumulator takes
+// the k-steps, operands and MFMAs of conv3x3_kernel in the same order and
+// the epilogues are the same operations, so both passes give the same bits.
+// The next layer's weights are loaded into registers while a layer computes.
+struct NetArgs {
+  const float2* x;            // network input fields [B][H][W]
+  float2* pred;               // prediction
+  const uint16_t* w[6];       // forward-layout BF16 weights of each layer
+  const float* bias[6];       // FP32 biases
+  int H, W;
+  int project;                // MSD projection of the boundary ring
+  double* tile_mass;          // or null: per 16x16 tile, sum of |pred|^2
+};
+
+constexpr int kNetWaves = 8;
+constexpr int kNetThreads = 64 * kNetWaves;
+constexpr int kNetPre = (48 * 9 * 48 / 8 + kNetThreads - 1) / kNetThreads;  // 16-byte weight chunks per thread
+
+template <int CIN, int COUT>
+__device__ __forceinline__ void net_load_w(const uint16_t* w, uint4 (&r)[kNetPre], int tid) {
+  constexpr int N = COUT * 9 * CIN / 8;
+  const uint4* src = reinterpret_cast<const uint4*>(w);
+#pragma unroll
+  for (int k = 0; k < kNetPre; ++k) {
+    const int i = tid + kNetThreads * k;
+    uint4 v = zero4();
+    if (i < N) v = src[i];
+    r[k] = v;
+  }
+}
+
+// weights [COUT][9 CIN] into LDS rows padded to 9 CIN + 8 values
+template <int CIN, int COUT>
+__device__ __forceinline__ void net_put_w(uint16_t* sW, const uint4 (&r)[kNetPre], int tid) {
+  constexpr int K = 9 * CIN, KP = K + 8, N = COUT * K / 8;
+  uint4* dst = reinterpret_cast<uint4*>(sW);
+#pragma unroll
+  for (int k = 0; k < kNetPre; ++k) {
+    const int i = tid + kNetThreads * k;
+    if (i < N) {
+      const int row = i / (K / 8), c = i - row * (K / 8);
+      dst[row * (KP / 8) + c] = r[k];
+    }
+  }
+}
+
+// The layer's input offset of every (k-step, lane group): k0 = 32 ks + 8 g =
+// tap CIN + ci0, tap = 3 dy + dx -> (ci0 / 8) SI^2 + dy SI + dx
+template <int CIN>
+__device__ __forceinline__ void net_put_off(int* sOff, int SI, int tid) {
+  constexpr int K = 9 * CIN, KSTEPS = (K + 31) / 32;
+  if (tid < 4 * KSTEPS) {
+    const int k0 = 32 * (tid >> 2) + 8 * (tid & 3);
+    int off = 0;
+    if (k0 < K) {
+      const int tap = k0 / CIN, ci0 = k0 - tap * CIN;
+      const int dy = tap / 3, dx = tap - 3 * dy;
+      off = (ci0 >> 3) * SI * SI + dy * SI + dx;
+    }
+    sOff[tid] = off;
+  }
+}
+
+// One layer: activation region `in` (SI x SI pixels) -> region of
+// SO = SI - 2 pixels whose first pixel is (gx0, gy0) in image `img`.  Wave w
+// takes the pixel-block pairs w, w + kNetWaves, ... (16 pixels per block, in
+// region order); on the last layer (SO = 16) that is rows 2w, 2w + 1 of the
+// tile, the rows conv3x3_kernel gives its wave w.
+template <int CIN, int COUT, bool LAST>
+__device__ __forceinline__ void net_layer(NetArgs a, const float* bias, const uint16_t* sW, const uint16_t* in, int SI,
+                                          uint16_t* out, int gx0, int gy0, int64_t img, double* sMass, int t,
+                                          const float2 (&xq)[2], const int* sOff) {
+  constexpr int K = 9 * CIN;
+  constexpr int KP = K + 8;
+  constexpr int KSTEPS = (K + 31) / 32;
+  constexpr int NCB = COUT / 16;
+  const int SO = SI - 2, npo = SO * SO, npi = SI * SI;
+  const int npairs = (npo + 31) / 32;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, g = lane >> 4;
+  double mass = 0.0;
+  for (int q = wave; q < npairs; q += kNetWaves) {
+    int base[2];
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int n = min(32 * q + 16 * rr + j, npo - 1);
+      const int py = n / SO, px = n - py * SO;
+      base[rr] = py * SI + px;
+    }
+    f32x4 acc[NCB][2];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // operands of k-step ks (weights: 16 output channels x 32 k; input: 32 k
+    // x 16 pixels), two sets: the LDS reads of step ks + 1 are in flight
+    // while the matrix cores work on step ks (each accumulator still sums
+    // the k-steps in ascending order)
+    // Operands of k-step ks (weights: 16 output channels x 32 k; input: 32 k
+    // x 16 pixels).  The input offset of lane group g comes from the layer's
+    // table, (ci0 / 8) npi + dy SI + dx for k0 = 32 ks + 8 g = CIN tap + ci0;
+    // the entry of step ks + 1 is read while step ks loads.  The first
+    // KF = K / 32 steps have every lane group in range; K = 432 or 72 leaves
+    // one partial step, peeled off the loop, whose out-of-range groups read
+    // in-range operands (offset 0) and mask them to zero.  Two operand sets:
+    // the reads of step ks + 1 are in flight while the matrix cores work on
+    // step ks; each accumulator sums the k-steps in ascending order.
+    constexpr int KF = K / 32;
+    constexpr bool TAIL = K % 32 != 0;
+    static_assert(KF >= 2, "at least two full k-steps");
+    int offn = sOff[g];
+    auto frags = [&](int ks, bf16x8 (&af)[NCB], bf16x8 (&bfr)[2]) {
+      const int off = offn;
+      if (ks + 1 < KSTEPS) offn = sOff[4 * (ks + 1) + g];
+      const int k0 = 32 * ks + 8 * g;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) af[cb] = as_bf16x8(*reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * KP + k0]));
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr) bfr[rr] = as_bf16x8(*reinterpret_cast<const uint4*>(&in[(off + base[rr]) * 8]));
+    };
+    auto frags_tail = [&](bf16x8 (&af)[NCB], bf16x8 (&bfr)[2]) {
+      const int k0 = 32 * KF + 8 * g;
+      const uint32_t msk = k0 < K ? 0xffffffffu : 0u;  // offn is 0 where k0 >= K
+      const int kc = k0 < K ? k0 : 0;
+      auto mask = [&](uint4 v) { return make_uint4(v.x & msk, v.y & msk, v.z & msk, v.w & msk); };
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        af[cb] = as_bf16x8(mask(*reinterpret_cast<const uint4*>(&sW[(16 * cb + j) * KP + kc])));
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr)
+        bfr[rr] = as_bf16x8(mask(*reinterpret_cast<const uint4*>(&in[(offn + base[rr]) * 8])));
+    };
+    auto mfmas = [&](const bf16x8 (&af)[NCB], const bf16x8 (&bfr)[2]) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int rr = 0; rr < 2; ++rr)
+          acc[cb][rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[cb], bfr[rr], acc[cb][rr], 0, 0, 0);
+    };
+    bf16x8 a0[NCB], b0[2], a1[NCB], b1[2];
+    frags(0, a0, b0);
+#pragma unroll 1
+    for (int ks = 0; ks + 2 < KF; ks += 2) {
+      frags(ks + 1, a1, b1);
+      mfmas(a0, b0);
+      frags(ks + 2, a0, b0);
+      mfmas(a1, b1);
+    }
+    // a0 holds full step KE; the full step KE + 1 (if any) and the tail remain
+    constexpr int KE = 2 * ((KF - 1) / 2);
+    if constexpr (KE + 1 < KF) {
+      frags(KE + 1, a1, b1);
+      mfmas(a0, b0);
+      if constexpr (TAIL) {
+        frags_tail(a0, b0);
+        mfmas(a1, b1);
+        mfmas(a0, b0);
+      } else {
+        mfmas(a1, b1);
+      }
+    } else {
+      if constexpr (TAIL) {
+        frags_tail(a1, b1);
+        mfmas(a0, b0);
+        mfmas(a1, b1);
+      } else {
+        mfmas(a0, b0);
+      }
+    }
+    // lane holds D[co = 16 cb + 4 g + r][pixel n], r = 0..3
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int n = 32 * q + 16 * rr + j;
+      if (n >= npo) continue;
+      const int py = n / SO, px = n - py * SO;
+      const int gy = gy0 + py, gx = gx0 + px;
+      const int64_t pix = img + (int64_t)gy * a.W + gx;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const int co = 16 * cb + 4 * g;
+        float v[4] = {acc[cb][rr][0], acc[cb][rr][1], acc[cb][rr][2], acc[cb][rr][3]};
+        if constexpr (LAST) {
+          if (g == 0) {  // channels 0, 1 are the real and imaginary increments
+            const float2 xv = xq[rr];  // a.x[pix], loaded when the tile started
+            float2 p = make_float2(xv.x + (v[0] + bias[0]), xv.y + (v[1] + bias[1]));
+            if (a.project && (gy == 0 || gy == a.H - 1 || gx == 0 || gx == a.W - 1)) {
+              // the operations of msd_project_kernel, so both give the same bits
+              const float mi = sqrtf(xv.x * xv.x + xv.y * xv.y), mo = sqrtf(p.x * p.x + p.y * p.y);
+              if (mo > 0.f) p = make_float2(p.x * (mi / mo), p.y * (mi / mo));
+            }
+            a.pred[pix] = p;
+            mass += (double)p.x * p.x + (double)p.y * p.y;
+          }
+        } else {
+          uint2 o = make_uint2(0u, 0u);
+          if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + bias[co + r], 0.f);
+            o.x = (uint32_t)bf16_bits(v[0]) | ((uint32_t)bf16_bits(v[1]) << 16);
+            o.y = (uint32_t)bf16_bits(v[2]) | ((uint32_t)bf16_bits(v[3]) << 16);
+          }
+          *reinterpret_cast<uint2*>(&out[((co >> 3) * npo + n) * 8 + (co & 7)]) = o;
+        }
+      }
+    }
+  }
+  if constexpr (LAST) {
+    // tile mass in the order of conv3x3_kernel: lanes (a fixed shuffle
+    // tree), then the waves that hold rows in ascending order
+    if (a.tile_mass) {
+      for (int off = 32; off >= 1; off >>= 1) mass += __shfl_xor(mass, off, 64);
+      if (lane == 0 && wave < 8) sMass[wave] = mass;
+      __syncthreads();
+      if (tid == 0) {
+        double t_m = 0.0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) t_m += sMass[w];
+        a.tile_mass[t] = t_m;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kNetThreads, 1) void net_forward_kernel(NetArgs a, int ntiles) {
+  // weights of one layer; regions: X = input (28^2 x 8), layer 2 (24^2 x 48),
+  // layer 4 (20^2 x 48); Y = layer 1 (26^2 x 48), layer 3, layer 5
+  __shared__ __attribute__((aligned(16))) uint16_t sW[48 * (9 * 48 + 8)];
+  __shared__ __attribute__((aligned(16))) uint16_t sX[24 * 24 * 48];
+  __shared__ __attribute__((aligned(16))) uint16_t sY[26 * 26 * 48];
+  __shared__ double sMass[8];
+  __shared__ float sBias[5 * 48 + 2];
+  __shared__ int sOff[14 * 4];  // input offsets of the current layer's k-steps
+  const int tid = threadIdx.x;
+  const int tilesx = a.W / 16, tilesy = a.H / 16;
+  // biases once (the last layer has 2 real output channels); visible after
+  // the first barrier of the tile loop
+  for (int i = tid; i < 5 * 48 + 2; i += kNetThreads) {
+    const int l = i / 48, c = i - l * 48;
+    sBias[i] = a.bias[l][c];
+  }
+  uint4 wr[kNetPre];
+  float2 xq[2];  // last layer: the input at this lane's two output pixels
+  int t = blockIdx.x;
+  if (t < ntiles) net_load_w<8, 48>(a.w[0], wr, tid);
+  for (; t < ntiles; t += gridDim.x) {
+    const int b = t / (tilesx * tilesy);
+    const int ty = (t / tilesx) % tilesy, tx = t % tilesx;
+    const int x0 = tx * 16, y0 = ty * 16;
+    const int64_t img = (int64_t)b * a.H * a.W;
+    {
+      const int wave = tid >> 6, j = tid & 15;
+#pragma unroll
+      for (int rr = 0; rr < 2; ++rr)
+        xq[rr] = (wave < 8 && (tid & 63) < 16) ? a.x[img + (int64_t)(y0 + 2 * wave + rr) * a.W + x0 + j]
+                                                : make_float2(0.f, 0.f);
+    }
+    __syncthreads();  // the previous tile's reads of sW and sY are done
+    net_put_w<8, 48>(sW, wr, tid);
+    net_put_off<8>(sOff, 28, tid);
+    // network input on the tile plus a 6-pixel ring: (re, im, 0, ..., 0) as
+    // BF16, zero outside the image (the conversion of pack_input_kernel)
+    for (int p = tid; p < 28 * 28; p += kNetThreads) {
+      const int py = p / 28, px = p - py * 28;
+      const int gy = y0 - 6 + py, gx = x0 - 6 + px;
+      uint4 o = zero4();
+      if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W) {
+        const float2 v = a.x[img + (int64_t)gy * a.W + gx];
+        o.x = (uint32_t)bf16_bits(v.x) | ((uint32_t)bf16_bits(v.y) << 16);
+      }
+      reinterpret_cast<uint4*>(sX)[p] = o;
+    }
+    __syncthreads();
+    net_load_w<48, 48>(a.w[1], wr, tid);
+    net_layer<8, 48, false>(a, sBias + 0, sW, sX, 28, sY, x0 - 5, y0 - 5, img, sMass, t, xq, sOff);
+    __syncthreads();
+    net_put_w<48, 48>(sW, wr, tid);
+    net_put_off<48>(sOff, 26, tid);
+    __syncthreads();
+    net_load_w<48, 48>(a.w[2], wr, tid);
+    net_layer<48, 48, false>(a, sBias + 48, sW, sY, 26, sX, x0 - 4, y0 - 4, img, sMass, t, xq, sOff);
+    __syncthreads();
+    net_put_w<48, 48>(sW, wr, tid);
+    net_put_off<48>(sOff, 24, tid);
+    __syncthreads();
+    net_load_w<48, 48>(a.w[3], wr, tid);
+    net_layer<48, 48, false>(a, sBias + 96, sW, sX, 24, sY, x0 - 3, y0 - 3, img, sMass, t, xq, sOff);
+    __syncthreads();
+    net_put_w<48, 48>(sW, wr, tid);
+    net_put_off<48>(sOff, 22, tid);
+    __syncthreads();
+    net_load_w<48, 48>(a.w[4], wr, tid);
+    net_layer<48, 48, false>(a, sBias + 144, sW, sY, 22, sX, x0 - 2, y0 - 2, img, sMass, t, xq, sOff);
+    __syncthreads();
+    net_put_w<48, 48>(sW, wr, tid);
+    net_put_off<48>(sOff, 20, tid);
+    __syncthreads();
+    net_load_w<48, 16>(a.w[5], wr, tid);
+    net_layer<48, 48, false>(a, sBias + 192, sW, sX, 20, sY, x0 - 1, y0 - 1, img, sMass, t, xq, sOff);
+    __syncthreads();
+    net_put_w<48, 16>(sW, wr, tid);
+    net_put_off<48>(sOff, 18, tid);
+    __syncthreads();
+    if (t + (int)gridDim.x < ntiles) net_load_w<8, 48>(a.w[0], wr, tid);
+    net_layer<48, 16, true>(a, sBias + 240, sW, sY, 18, nullptr, x0, y0, img, sMass, t, xq, sOff);
+  }
+}
+
 // ---------------------------------------------------------------- loss
 
 // d = pred - target; partial sums of |d|^2 per workgroup (FP64, fixed order);
@@ -714,6 +1031,25 @@ hipError_t sg_conv(int kind, const SgConv& c, hipStream_t st) {
     case kSgDgradHidden: return launch_conv<48, 48, kEpiDgrad>(a, ntiles, st);
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t sg_net_forward(const SgNet& c, hipStream_t st) {
+  NetArgs a;
+  a.x = static_cast<const float2*>(c.x);
+  a.pred = static_cast<float2*>(c.pred);
+  for (int l = 0; l < 6; ++l) {
+    a.w[l] = c.w[l];
+    a.bias[l] = c.bias[l];
+  }
+  a.H = c.H;
+  a.W = c.W;
+  a.project = c.project;
+  a.tile_mass = c.tile_mass;
+  const int ntiles = c.B * (c.H / 16) * (c.W / 16);
+  // one workgroup per CU (its LDS), persistent over the tiles
+  const dim3 grid((unsigned)std::min(ntiles, cu_count()));
+  hipLaunchKernelGGL(net_forward_kernel, grid, dim3(kNetThreads), 0, st, a, ntiles);
   return hipGetLastError();
 }
 

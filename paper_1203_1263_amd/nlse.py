@@ -28,6 +28,7 @@ NLSE_F32, NLSE_F64 = 0, 1
 NLSE_CD2, NLSE_2SHOC = 2, 4
 NLSE_BC_DIRICHLET, NLSE_BC_MSD, NLSE_BC_L0 = 0, 1, 2
 NLSE_COMPENSATED = 0x1
+NLSE_SG_PATH_AUTO, NLSE_SG_PATH_LAYERS, NLSE_SG_PATH_FUSED = 0, 1, 2
 NLSE_NO_GRAPH = 0x2
 NLSE_FUSED_PAIRS = 0x4
 
@@ -112,6 +113,8 @@ def load_library() -> ctypes.CDLL:
         "nlse_surrogate_block": (ctypes.c_int, [vp, vp, vp, ctypes.c_int, ctypes.c_int, dp]),
         "nlse_surrogate_advance": (ctypes.c_int, [vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                                   ctypes.c_int64, ctypes.c_double, i64p]),
+        "nlse_surrogate_set_path": (ctypes.c_int, [vp, ctypes.c_int]),
+        "nlse_surrogate_fused_max_batch": (ctypes.c_int, [vp]),
         "nlse_surrogate_destroy": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
@@ -339,6 +342,16 @@ def nlse_surrogate_advance(m, g, order, bc, dt, nblocks, drift_tol):
     _check(load_library().nlse_surrogate_advance(m, g, order, bc, dt, nblocks, drift_tol, ctypes.byref(nf)),
            "nlse_surrogate_advance")
     return nf.value
+
+
+def nlse_surrogate_set_path(m, path: int):
+    _check(load_library().nlse_surrogate_set_path(m, path), "nlse_surrogate_set_path")
+
+
+def nlse_surrogate_fused_max_batch(m) -> int:
+    r = load_library().nlse_surrogate_fused_max_batch(m)
+    _check(min(r, 0), "nlse_surrogate_fused_max_batch")
+    return r
 
 
 def nlse_surrogate_destroy(m):
@@ -614,6 +627,15 @@ class Surrogate:
     def project_msd(self, psi_in, psi_out):
         b = self._check_fields(psi_in)
         nlse_surrogate_project_msd(self._m, psi_in.data_ptr(), psi_out.data_ptr(), b)
+
+    def set_path(self, path):
+        """Inference kernels: "auto", "layers" (one kernel per layer) or
+        "fused" (all six layers in one kernel); the same bits either way."""
+        nlse_surrogate_set_path(self._m, {"auto": NLSE_SG_PATH_AUTO, "layers": NLSE_SG_PATH_LAYERS,
+                                          "fused": NLSE_SG_PATH_FUSED}[path] if isinstance(path, str) else path)
+
+    def fused_max_batch(self) -> int:
+        return nlse_surrogate_fused_max_batch(self._m)
 
     def advance(self, grid, order, bc, dt, nblocks, drift_tol):
         return nlse_surrogate_advance(self._m, grid._g, order, BC[bc] if isinstance(bc, str) else bc, dt,

@@ -34,6 +34,7 @@ hipError_t nlse_launch_batch(const nlse::BatchLaunch&, hipStream_t) { return hip
 hipError_t nlse_batch_occupancy(int, int, int, int, int, int*) { return hipErrorNotSupported; }
 hipError_t sg_pack_input(const void*, void*, int64_t, hipStream_t) { return hipErrorNotSupported; }
 hipError_t sg_conv(int, const SgConv&, hipStream_t) { return hipErrorNotSupported; }
+hipError_t sg_net_forward(const SgNet&, hipStream_t) { return hipErrorNotSupported; }
 hipError_t sg_loss(const void*, const void*, uint16_t*, double*, int, int64_t, hipStream_t) {
   return hipErrorNotSupported;
 }

@@ -266,3 +266,11 @@ def test_noalloc_mass_energy_rejects_before_any_device_call():
     with pytest.raises(nlse.NLSEError) as e:
         nlse.nlse_mass_energy_noalloc(**dict(ok, dims=[1024, 1024, 257]))
     assert "static scratch" in str(e.value)
+
+
+def test_surrogate_path_calls_validate_their_model(lib):
+    vp = ctypes.c_void_p
+    lib.nlse_surrogate_set_path.argtypes = [vp, ctypes.c_int]
+    lib.nlse_surrogate_fused_max_batch.argtypes = [vp]
+    assert lib.nlse_surrogate_set_path(None, nlse.NLSE_SG_PATH_FUSED) == nlse.NLSE_EINVAL
+    assert lib.nlse_surrogate_fused_max_batch(None) == nlse.NLSE_EINVAL

@@ -375,3 +375,39 @@ def test_block_equals_forward_projection_and_mass():
         m.block(x, plain, project_msd=False)
         assert torch.equal(plain, m.forward(x))
     m.close()
+
+
+@pytest.mark.parametrize("H,W,B", [(32, 48, 1), (48, 32, 3), (256, 256, 1), (256, 256, 3)])
+def test_fused_network_pass_equals_layer_by_layer(H, W, B):
+    """The whole-network kernel (one workgroup takes a 16x16 tile through all
+    six layers, activations in LDS, the ring each later layer reads
+    recomputed) gives the bits of the layer-by-layer pass: forward, and the
+    block with and without the MSD projection, masses included.  Image
+    borders on every side (32x48: every tile touches one), several tiles per
+    workgroup at 256^2 batch 3 (768 tiles over one workgroup per CU)."""
+    import torch
+    m, p, _ = make(H, W, B, seed=61)
+    x = torch.from_numpy(fields(B, H, W, 62).astype(np.complex64)).cuda()
+    res = {}
+    for path in ("layers", "fused"):
+        m.set_path(path)
+        fwd = m.forward(x)
+        blk = torch.empty_like(x)
+        M = m.block(x, blk)
+        plain = torch.empty_like(x)
+        M0 = m.block(x, plain, project_msd=False)
+        torch.cuda.synchronize()
+        res[path] = (fwd, blk, M, plain, M0)
+    (fl, bl, Ml, pl, M0l), (ff, bf, Mf, pf, M0f) = res["layers"], res["fused"]
+    assert torch.isfinite(torch.view_as_real(fl)).all()
+    assert torch.equal(fl.view(torch.int64), ff.view(torch.int64))
+    assert torch.equal(bl.view(torch.int64), bf.view(torch.int64))
+    assert torch.equal(pl.view(torch.int64), pf.view(torch.int64))
+    assert list(Ml) == list(Mf) and list(M0l) == list(M0f)
+    # and the pass is the network: within 3e-2 of the FP64 reference
+    x64 = x.cpu().numpy().astype(np.complex128)
+    rf, _ = S.forward(p, x64)
+    assert rel_l2(ff.cpu().numpy().astype(np.complex128) - x64, rf - x64) < 3e-2
+    m.set_path("auto")
+    assert m.fused_max_batch() >= 1
+    m.close()
