@@ -367,7 +367,8 @@ def surrogate_summary(args):
             "mass_drift_per_block_max", "fallbacks", "blocks", "rel_l2_guarded")
     out = {k: res[k] for k in keep}
     for b in ("speedup_b1", "speedup_b64"):
-        out[b] = {k: res[b][k] for k in ("batch", "ms_rk4_16_steps", "rk4_config", "ms_surrogate_block", "speedup")}
+        out[b] = {k: res[b][k] for k in ("batch", "ms_rk4_16_steps", "rk4_config", "ms_surrogate_block", "speedup",
+                                         "path", "ms_surrogate_block_layers") if k in res[b]}
     # the speedup holds for as many blocks as stay within the 1e-2 error bar
     out["speedup_within_1e-2"] = {"blocks": res["blocks_within_1e-2"],
                                   "batch_1": res["speedup_b1"]["speedup"], "batch_64": res["speedup_b64"]["speedup"]}

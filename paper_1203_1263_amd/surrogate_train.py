@@ -242,12 +242,21 @@ def speedup(m, snaps, batch: int):
         tx, ty, wg, pairs = b.config()
         rk_config = {"stage_pairs": bool(pairs), "tile": [tx, ty], "wg_per_cu": wg}
         b.close()
+    # inference kernels the block takes: the whole-network kernel for small
+    # batches, one kernel per layer otherwise (the same bits either way)
+    path = "fused" if batch <= m.fused_max_batch() else "layers"
     t_sg = _time(surrogate_block, 10)
     t_fwd = _time(lambda: m.forward(fields, out), 10)
+    extra = {}
+    if path == "fused":
+        m.set_path("layers")
+        extra = {"ms_surrogate_block_layers": _time(surrogate_block, 10),
+                 "ms_forward_layers": _time(lambda: m.forward(fields, out), 10)}
+        m.set_path("auto")
     fwd_flop = FLOP_PER_PIXEL * batch * N * N
     fwd_bytes = BYTES_PER_PIXEL * batch * N * N
     return {"batch": batch, "ms_rk4_16_steps": t_rk, "rk4_config": rk_config, "ms_surrogate_block": t_sg,
-            "speedup": t_rk / t_sg,
+            "speedup": t_rk / t_sg, "path": path, **extra,
             "ms_forward": t_fwd, "forward_tflops": fwd_flop / (t_fwd * 1e-3) / 1e12,
             "forward_gbs": fwd_bytes / (t_fwd * 1e-3) / 1e9}
 
