@@ -211,11 +211,18 @@ int nlse_set_state(nlse_grid *g, const void *lo_dev);
  * field is not changed; for fused 3D grids only the z-chunk of the 32x8
  * tile is tuned, for 2D grids with NLSE_FUSED_PAIRS the pair tile, 32x32
  * or 64x16), keeps the fastest and stores it in the cache file
- * named by $NLSE_TUNE_CACHE if set.  nlse_set_tile forces a shape
- * (NLSE_EUNSUPPORTED if it is not a compiled candidate). */
+ * named by $NLSE_TUNE_CACHE if set.  On 2D grids without NLSE_FUSED_PAIRS
+ * it also times the first stage pair on both pair tiles against stages 1
+ * and 2 on the best four-pass tile, and runs later steps of this order as
+ * stage pairs if they were faster (the same bits; see NLSE_FUSED_PAIRS).
+ * nlse_set_tile forces a shape run as four passes unless the grid has
+ * NLSE_FUSED_PAIRS (NLSE_EUNSUPPORTED if it is not a compiled candidate).
+ * nlse_get_stage_pairs sets *on to 1 if steps of `order` run as stage pairs
+ * with the current settings (3D: except under the L0 condition). */
 int nlse_autotune(nlse_grid *g, int order, int bc, double dt);
 int nlse_get_tile(const nlse_grid *g, int order, int tile[3]);
 int nlse_set_tile(nlse_grid *g, int order, const int tile[3]);
+int nlse_get_stage_pairs(const nlse_grid *g, int order, int *on);
 
 /* Destroy a grid: frees library-internal host objects and graphs only. */
 int nlse_destroy_grid(nlse_grid *g);

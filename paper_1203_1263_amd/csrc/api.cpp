@@ -144,6 +144,9 @@ struct nlse_grid {
   hipStream_t stream;
   const void* V;
   int tile[2][3];  // [0] CD2, [1] 2SHOC
+  // 2D grids without NLSE_FUSED_PAIRS: stage pairs chosen by nlse_autotune
+  // because they timed faster (per order slot, on a pair tile only)
+  bool auto_pairs[2] = {false, false};
   hipStream_t cap = nullptr;  // private stream used only for graph capture
   std::map<GraphKey, hipGraphExec_t> graphs;
   hipStream_t copy = nullptr;  // frames: device-to-host copies
@@ -199,6 +202,7 @@ static bool fused_eligible(const Shape& s, int dtype, unsigned flags, int order)
 // launches (every type, scheme and boundary condition) on the 64x16 tile if
 // that is its tile, else on 32x32.
 static bool pairs2d_eligible(const Shape& s, unsigned flags) { return s.ndim == 2 && (flags & NLSE_FUSED_PAIRS); }
+static bool pair2d_tile(const int t[3]) { return (t[0] == 32 && t[1] == 32) || (t[0] == 64 && t[1] == 16); }
 
 static void default_tile(const Shape& s, int dtype, unsigned flags, int order, int t[3]) {
   if (s.ndim == 1) {
@@ -228,6 +232,13 @@ static void default_tile(const Shape& s, int dtype, unsigned flags, int order, i
 }
 
 static int tile_slot(int order) { return order == 4 ? 1 : 0; }
+
+// Whether steps of `order` on this grid with this tile run as stage pairs:
+// always with NLSE_FUSED_PAIRS, else when the autotuner chose them.
+static bool runs_pairs2d(const nlse_grid* g, int order, const int tile[3]) {
+  if (g->shape.ndim != 2) return false;
+  return (g->flags & NLSE_FUSED_PAIRS) || (g->auto_pairs[tile_slot(order)] && pair2d_tile(tile));
+}
 
 extern "C" int nlse_create_grid(nlse_grid** g, int ndim, const int64_t dims[3], double h, double a, double s,
                                 int dtype, unsigned flags, void* psi_dev, void* work_dev, size_t work_bytes,
@@ -361,7 +372,7 @@ static hipError_t enqueue_steps(const nlse_grid* g, int order, int bc, double dt
     return nlse_launch_resident1d(L, nsteps, dt, st);
   }
   int64_t left = nsteps;
-  if (pairs2d_eligible(g->shape, g->flags)) {
+  if (runs_pairs2d(g, order, tile)) {
     // Pairs of steps Psi -> workspace -> Psi, as below; the first pass of
     // each step writes U2 to bufA
     nlse::StageLaunch L = grid_launch(g, order, bc, tile);
@@ -704,6 +715,10 @@ extern "C" int nlse_set_tile(nlse_grid* g, int order, const int tile[3]) {
     return fail(NLSE_EUNSUPPORTED, "tile %dx%dx%d is not a compiled candidate for this grid", tile[0], tile[1],
                 tile[2]);
   memcpy(g->tile[tile_slot(order)], tile, 3 * sizeof(int));
+  if (g->auto_pairs[tile_slot(order)]) {  // a forced shape runs as four passes
+    g->auto_pairs[tile_slot(order)] = false;
+    drop_graphs(g);
+  }
   return NLSE_OK;
 }
 
@@ -800,9 +815,24 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
   if (rc) return rc;
   if (!(dt > 0) || !std::isfinite(dt)) return fail(NLSE_EINVAL, "dt must be finite and > 0");
   const std::string key = cache_key(g, order, bc);
-  int cached[3];
-  if (nlse_cache_lookup(key, cached, 3) && tile_fits(g, order, cached)) {
-    memcpy(g->tile[tile_slot(order)], cached, sizeof cached);
+  const int slot = tile_slot(order);
+  // 2D grids without NLSE_FUSED_PAIRS also choose between four passes and
+  // stage pairs (the same bits either way)
+  const bool choose_pairs = g->shape.ndim == 2 && !(g->flags & NLSE_FUSED_PAIRS);
+  auto set_pairs = [&](bool on) {
+    if (g->auto_pairs[slot] != on) drop_graphs(g);
+    g->auto_pairs[slot] = on;
+  };
+  int cached[4];
+  if (choose_pairs) {
+    if (nlse_cache_lookup(key + " auto", cached, 4) && tile_fits(g, order, cached) &&
+        (cached[3] == 0 || pair2d_tile(cached))) {
+      memcpy(g->tile[slot], cached, 3 * sizeof(int));
+      set_pairs(cached[3] != 0);
+      return NLSE_OK;
+    }
+  } else if (nlse_cache_lookup(key, cached, 3) && tile_fits(g, order, cached)) {
+    memcpy(g->tile[slot], cached, 3 * sizeof(int));
     return NLSE_OK;
   }
   auto cands = candidates(g, order);
@@ -879,10 +909,79 @@ extern "C" int nlse_autotune(nlse_grid* g, int order, int bc, double dt) {
       best_t = t;
     }
   }
+  // Four passes or stage pairs: stages 1 and 2 at the best four-pass tile
+  // against the first stage pair (stages 1 + 2 in one pass) on each pair
+  // tile; both leave Psi untouched, and the second halves of a step compare
+  // alike (stages 3 and 4 against the second pair).
+  bool pick_pairs = false;
+  if (e == hipSuccess && choose_pairs) {
+    auto timed = [&](auto&& run, float* ms) -> hipError_t {
+      hipError_t ee = run(1);  // warm-up
+      if (ee != hipSuccess) return ee;
+      (void)hipEventRecord(e0, g->stream);
+      if ((ee = run(reps)) != hipSuccess) return ee;
+      (void)hipEventRecord(e1, g->stream);
+      if ((ee = hipEventSynchronize(e1)) != hipSuccess) return ee;
+      return hipEventElapsedTime(ms, e0, e1);
+    };
+    float t4 = 0.f;
+    for (int d = 0; d < 3; ++d) L.tile[d] = best_t[d];
+    e = timed(
+        [&](int n) -> hipError_t {
+          for (int r = 0; r < n; ++r)
+            for (int k = 1; k <= 2; ++k) {
+              L.stage = k;
+              L.uin = k == 1 ? g->psi : A;
+              L.uout = k == 2 ? B : A;
+              L.c_acc = k == 1 ? dt / 6.0 : dt / 3.0;
+              L.c_next = dt / 2.0;
+              hipError_t ee = nlse_launch_stage(L, g->stream);
+              if (ee != hipSuccess) return ee;
+            }
+          return hipSuccess;
+        },
+        &t4);
+    for (auto pt : {std::array<int, 3>{32, 32, 1}, {64, 16, 1}}) {
+      if (e != hipSuccess || !tile_fits(g, order, pt.data())) continue;
+      for (int d = 0; d < 3; ++d) L.tile[d] = pt[d];
+      float tp = 0.f;
+      e = timed(
+          [&](int n) -> hipError_t {
+            for (int r = 0; r < n; ++r) {
+              hipError_t ee = nlse_launch_pair2d(L, g->psi, B, L.acc, A, nullptr, dt, 1, g->stream);
+              if (ee != hipSuccess) return ee;
+            }
+            return hipSuccess;
+          },
+          &tp);
+      if (e == hipSuccess && tp < t4) {
+        t4 = tp;
+        best_t = pt;
+        pick_pairs = true;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (e != hipSuccess) return hip_fail(e, "autotune launch");
-  memcpy(g->tile[tile_slot(order)], best_t.data(), 3 * sizeof(int));
-  nlse_cache_store(key, best_t.data(), 3, best / reps);
+  memcpy(g->tile[slot], best_t.data(), 3 * sizeof(int));
+  if (choose_pairs) {
+    set_pairs(pick_pairs);
+    const int rec[4] = {best_t[0], best_t[1], best_t[2], pick_pairs ? 1 : 0};
+    nlse_cache_store(key + " auto", rec, 4, best / reps);
+  } else {
+    nlse_cache_store(key, best_t.data(), 3, best / reps);
+  }
+  return NLSE_OK;
+}
+
+extern "C" int nlse_get_stage_pairs(const nlse_grid* g, int order, int* on) {
+  if (!g || !on) return fail(NLSE_EINVAL, "NULL argument");
+  if (order != 2 && order != 4) return fail(NLSE_EINVAL, "bad order");
+  const int* t = g->tile[tile_slot(order)];
+  *on = (runs_pairs2d(g, order, t) ||
+         (fused_eligible(g->shape, g->dtype, g->flags, order) && t[0] == 32 && t[1] == 8))
+            ? 1
+            : 0;
   return NLSE_OK;
 }

@@ -84,6 +84,7 @@ def load_library() -> ctypes.CDLL:
         "nlse_set_state": (ctypes.c_int, [vp, vp]),
         "nlse_autotune": (ctypes.c_int, [vp, ctypes.c_int, ctypes.c_int, ctypes.c_double]),
         "nlse_get_tile": (ctypes.c_int, [vp, ctypes.c_int, ip]),
+        "nlse_get_stage_pairs": (ctypes.c_int, [vp, ctypes.c_int, ip]),
         "nlse_set_tile": (ctypes.c_int, [vp, ctypes.c_int, ip]),
         "nlse_destroy_grid": (ctypes.c_int, [vp]),
         "nlse_batch_workspace_bytes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(SimDesc), ctypes.c_int,
@@ -213,6 +214,12 @@ def nlse_get_tile(g, order: int):
 def nlse_set_tile(g, order: int, tile):
     t = (ctypes.c_int * 3)(*tile)
     _check(load_library().nlse_set_tile(g, order, t), "nlse_set_tile")
+
+
+def nlse_get_stage_pairs(g, order: int) -> bool:
+    on = ctypes.c_int(0)
+    _check(load_library().nlse_get_stage_pairs(g, order, ctypes.byref(on)), "nlse_get_stage_pairs")
+    return bool(on.value)
 
 
 def nlse_destroy_grid(g):
@@ -453,6 +460,10 @@ class Grid:
 
     def set_tile(self, order: int, tile):
         nlse_set_tile(self._g, order, tile)
+
+    def stage_pairs(self, order: int) -> bool:
+        """Whether steps of this order run as stage pairs now."""
+        return nlse_get_stage_pairs(self._g, order)
 
     def close(self):
         if self._g:

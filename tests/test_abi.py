@@ -274,3 +274,9 @@ def test_surrogate_path_calls_validate_their_model(lib):
     lib.nlse_surrogate_fused_max_batch.argtypes = [vp]
     assert lib.nlse_surrogate_set_path(None, nlse.NLSE_SG_PATH_FUSED) == nlse.NLSE_EINVAL
     assert lib.nlse_surrogate_fused_max_batch(None) == nlse.NLSE_EINVAL
+
+
+def test_stage_pairs_query_validates(lib):
+    on = ctypes.c_int(7)
+    assert lib.nlse_get_stage_pairs(None, 4, ctypes.byref(on)) == nlse.NLSE_EINVAL
+    assert on.value == 7

@@ -346,6 +346,41 @@ def test_autotune_pairs2d_keeps_field_and_picks_a_pair_tile():
     g.close()
 
 
+@pytest.mark.parametrize("shape,order,bc,dtype,comp", [
+    ((1024, 1024), 4, "msd", "f32", True),
+    ((177, 301), 2, "dirichlet", "f64", False),
+    ((96, 200), 4, "l0", "f32", False),
+])
+def test_autotune_may_choose_stage_pairs_with_four_pass_bits(shape, order, bc, dtype, comp):
+    """A 2D grid without NLSE_FUSED_PAIRS: the autotuner also times the
+    first stage pair against stages 1 and 2 and keeps pairs when faster.
+    Either way the field is untouched by tuning, the tuned run (odd step
+    count: pairs, then one four-pass step) equals four passes on the chosen
+    tile forced with nlse_set_tile, and nlse_set_tile turns pairs off."""
+    import torch
+    from paper_1203_1263_amd.nlse import Grid
+    from gpu_util import to_dev, pot_dev
+    u, V, h, a, s = smooth_problem(shape, 17)
+    dt = 0.5 * oracle.dt_max(2, order, h, a)
+    psi = to_dev(u, dtype)
+    before = psi.clone()
+    g = Grid(psi, h, a, s, V=pot_dev(V, dtype), compensated=comp)
+    g.autotune(order, bc, dt)
+    torch.cuda.synchronize()
+    assert torch.equal(psi, before)
+    tile, pairs = tuple(g.tile(order)), g.stage_pairs(order)
+    print(f"{shape} order {order} {bc} {dtype}{' comp' if comp else ''}: tile {tile}, stage pairs {pairs}")
+    if pairs:
+        assert tile in ((32, 32, 1), (64, 16, 1))
+    g.step(dt, 7, order=order, bc=bc)
+    tuned = psi.cpu().numpy()
+    ref = run_gpu(u, h, a, s, dt, 7, V=V, order=order, bc=bc, dtype=dtype, compensated=comp, tile=tile)
+    assert np.array_equal(tuned.astype(np.complex128), ref)
+    g.set_tile(order, tile)
+    assert not g.stage_pairs(order)
+    g.close()
+
+
 def test_checkpoint_restore_bitwise():
     """10 steps = 5 steps + (Psi, Psi_lo) saved into a fresh grid + 5 steps."""
     import torch
