@@ -152,6 +152,21 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, in
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
       for (int rr = 0; rr < RPW; ++rr) acc[cb][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // backward data from the 16-channel last layer: the ReLU mask of this
+    // lane's outputs is loaded before the k-loop so its latency overlaps the
+    // MFMAs (the 48-channel variant has no registers left for it: at 128 it
+    // spills and was measured slower, so it loads the mask in the epilogue)
+    constexpr bool kMaskEarly = EPI == kEpiDgrad && CIN < 48;
+    uint2 mk[RPW][NCB];
+    if constexpr (kMaskEarly) {
+#pragma unroll
+      for (int rr = 0; rr < RPW; ++rr)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int64_t pix = img + (int64_t)(y0 + RPW * wave + rr) * a.W + (x0 + j);
+          mk[rr][cb] = *reinterpret_cast<const uint2*>(a.mask + pix * COUT + 16 * cb + 4 * g);
+        }
+    }
 
     // operands of k-step ks (weights: 16 output channels x 32 k; input: 32 k
     // x 16 pixels of one row), read from LDS
@@ -213,7 +228,7 @@ __global__ __launch_bounds__(64 * NW, NW / 2) void conv3x3_kernel(ConvArgs a, in
 #pragma unroll
           for (int r = 0; r < 4; ++r) v[r] = fmaxf(v[r] + a.bias[co + r], 0.f);
         } else if constexpr (EPI == kEpiDgrad) {
-          const uint2 m = *reinterpret_cast<const uint2*>(a.mask + pix * COUT + co);
+          const uint2 m = kMaskEarly ? mk[rr][cb] : *reinterpret_cast<const uint2*>(a.mask + pix * COUT + co);
           const uint16_t mb[4] = {(uint16_t)(m.x & 0xffffu), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffffu),
                                   (uint16_t)(m.y >> 16)};
 #pragma unroll
